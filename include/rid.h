@@ -1,0 +1,268 @@
+/*
+ * rid.h -- C ABI of the MI355X (gfx950) rid-preconditioned Davidson library.
+ *
+ * The library solves the linear-response TDDFT problems of Zhou & Parker,
+ * "Converging TDDFT calculations in 5 iterations with minimal auxiliary
+ * preconditioning":
+ *   - the k lowest excitation energies of the TDA problem A X = Omega X
+ *     (Eq. TDA) or of the full problem (Eq. Casida), by a Davidson method
+ *     (Sec. 2.1, Fig. 1);
+ *   - the dynamic polarizability alpha_uv(omega) (Eq. TDDFT_polar) by a
+ *     Krylov linear solve;
+ * with either the diagonal preconditioner or the minimal-auxiliary ris model
+ * T applied through an inner Krylov solve (Eq. precondition, Sec. 3).
+ *
+ * Operators.  With orbital energies eps (occupied i, j; virtual a, b), a
+ * three-index tensor B^P_pq with (pq|rs) = sum_P B^P_pq B^P_rs (Eq.
+ * pqrs_approx, metric folded in) and exchange fraction a_x (c_x of
+ * Eq. hessian), the XC kernel dropped:
+ *   A   = diag(de) + 2K - a_x W,           B = 2K - a_x W',
+ *   A+B = diag(de) + 4K - a_x (W + W'),    A-B = diag(de) - a_x (W - W'),
+ * de_ia = eps_a - eps_i, K_{ia,jb} = (ia|jb), W_{ia,jb} = (ij|ab),
+ * W'_{ia,jb} = (ib|ja).  The ris model T has the same form built from the ris
+ * tensor: Coulomb from all naux_ris rows, exchange from the leading
+ * naux_ris_k rows (the (d, s) split of Sec. 3.2) and only over orbitals inside
+ * the energy window of Sec. 3.1 (virtuals with eps_a <= eps_HOMO + t_cut,
+ * occupieds with eps_i >= eps_LUMO - t_cut).
+ *
+ * Layouts.  Response vectors have length N = no*nv, index ia = i*nv + a; a
+ * block of n vectors is n contiguous vectors (row-major n x N).  Tensors are
+ * row-major: b_ia (naux, no, nv), b_ij (naux, no, no), b_ab (naux, nv, nv);
+ * the ij and ab slices must be symmetric.  Orbital energies are sorted
+ * ascending within the occupied and within the virtual set.
+ *
+ * Memory.  Every pointer named *_dev is device memory on the context's
+ * device; *_host is host memory.  Device tensors handed to
+ * rid_problem_create are borrowed: the caller keeps them alive until
+ * rid_problem_destroy and the library never frees or writes them.  All device
+ * memory the library needs comes from the context's allocator.
+ *
+ * Streams.  All work is enqueued on the context's stream.  Solve calls are
+ * synchronous: host outputs are valid on return, device outputs are written
+ * in stream order.
+ *
+ * Errors.  Every call returns a rid_status.  Negative values are errors; the
+ * message of the last error on a context is returned by rid_last_error.  No
+ * call writes outputs after returning an error other than
+ * RID_WARN_NOT_CONVERGED.  Handles are not thread-safe: use one context per
+ * host thread (the server is internally threaded).
+ */
+#ifndef RID_H_
+#define RID_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define RID_API __attribute__((visibility("default")))
+#else
+#define RID_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rid_status;
+
+#define RID_OK 0
+#define RID_WARN_NOT_CONVERGED 1   /* outputs written with the last Ritz values */
+#define RID_ERR_INVALID_ARG (-1)   /* null pointer, bad enum, bad option */
+#define RID_ERR_SHAPE (-2)         /* inconsistent or out-of-range dimensions */
+#define RID_ERR_DTYPE (-3)         /* unsupported tensor dtype */
+#define RID_ERR_NO_MEMORY (-4)     /* allocator failed or budget exceeded */
+#define RID_ERR_HIP (-5)           /* a HIP runtime call failed */
+#define RID_ERR_INDEFINITE (-6)    /* A-B (or its projection) not positive definite */
+#define RID_ERR_BREAKDOWN (-7)     /* every new direction dropped before convergence */
+#define RID_ERR_NEAR_SINGULAR (-8) /* frequency within the guard of a pole */
+#define RID_ERR_NO_DEVICE (-9)     /* no usable gfx950 device */
+#define RID_ERR_INTERNAL (-10)
+#define RID_ERR_CANCELLED (-11)    /* server request cancelled */
+#define RID_ERR_TIMEOUT (-12)      /* server wait timed out */
+#define RID_ERR_PENDING (-13)      /* server request not finished yet */
+
+typedef enum { RID_F64 = 0, RID_F32 = 1, RID_BF16 = 2 } rid_dtype;
+typedef enum { RID_PRECOND_DIAG = 0, RID_PRECOND_RIS = 1 } rid_precond;
+/* RID_PRECISION_FP64: every product in FP64.  RID_PRECISION_MIXED: outer
+ * products with FP32 operands (FP64 reduction of partial sums), ris products
+ * with BF16 operands and FP32 accumulation; subspace orthonormalisation and
+ * all projected (small dense) problems stay FP64. */
+typedef enum { RID_PRECISION_FP64 = 0, RID_PRECISION_MIXED = 1 } rid_precision;
+typedef enum { RID_TDA = 0, RID_RPA = 1 } rid_mode;
+/* Operators for rid_apply_operator. */
+typedef enum {
+  RID_OP_A = 0,     /* y = A x */
+  RID_OP_APB_AMB = 1, /* y = (A+B) x, y2 = (A-B) x */
+  RID_OP_T = 2,     /* y = T x (ris model of A) */
+  RID_OP_TPM = 3    /* y = T+ x, y2 = T- x (ris models of A+B, A-B) */
+} rid_operator;
+
+typedef struct rid_context rid_context;
+typedef struct rid_problem rid_problem;
+typedef struct rid_server rid_server;
+
+/* Device memory provider.  alloc returns a device pointer with at least
+ * 256-byte alignment or NULL; free releases it.  Both are called from the
+ * thread that calls into the library (or the server's worker thread). */
+typedef struct {
+  void* user;
+  void* (*alloc)(void* user, size_t bytes);
+  void (*free)(void* user, void* ptr);
+} rid_allocator;
+
+typedef struct {
+  int32_t no, nv;            /* occupied and virtual orbital counts, >= 1 */
+  int32_t naux;              /* rows of the full tensor, >= 1 */
+  int32_t naux_ris;          /* rows of the ris tensor, 0 = no ris tensor */
+  int32_t naux_ris_k;        /* leading ris rows used for exchange, 0..naux_ris */
+  double a_x;                /* exact-exchange fraction (c_x of Eq. hessian) */
+  double t_cut_ha;           /* exchange energy window of Sec. 3.1, Hartree; <= 0 or inf = none */
+  const double* eps_occ_host;  /* [no], ascending */
+  const double* eps_vir_host;  /* [nv], ascending */
+  const void* b_ia_dev;      /* (naux, no, nv) */
+  const void* b_ij_dev;      /* (naux, no, no) symmetric slices */
+  const void* b_ab_dev;      /* (naux, nv, nv) symmetric slices */
+  int32_t b_dtype;           /* RID_F64 */
+  const void* bris_ia_dev;   /* (naux_ris, no, nv) or NULL */
+  const void* bris_ij_dev;
+  const void* bris_ab_dev;
+  int32_t bris_dtype;        /* RID_F64 */
+} rid_problem_desc;
+
+typedef struct {
+  int32_t precond;       /* rid_precond */
+  int32_t precision;     /* rid_precision */
+  double tol;            /* outer residual threshold (1e-5, Sec. 3) */
+  int32_t max_iter;      /* outer iterations, >= 1 */
+  int32_t n_extra_init;  /* -1: min(k,3) for ris, 8 for diag (Sec. 3.2) */
+  double inner_tol;      /* inner relative threshold (1e-2, Sec. 3.1) */
+  int32_t inner_max_iter;/* inner iterations (20, Sec. 3.1) */
+  double init_tol;       /* ris initial-guess threshold (1e-3, Sec. 3.1) */
+  int32_t init_max_iter; /* ris initial-guess iterations (20) */
+  int32_t m_max;         /* subspace cap before restart, 0 = max(200, 40 k) */
+} rid_solve_opts;
+
+#define RID_MAX_HISTORY 128
+
+typedef struct {
+  int32_t n_iter;        /* outer block products, the first included */
+  int32_t n_mv;          /* vectors multiplied by the outer operator */
+  int32_t n_inner_mv;    /* vectors multiplied by T (preconditioner + guess) */
+  int32_t n_inner_iter;  /* inner block products */
+  int32_t n_history;
+  double history[RID_MAX_HISTORY]; /* max residual norm per outer iteration */
+  double t_matvec_ms;    /* outer operator products */
+  double t_precond_ms;   /* preconditioner and ris initial guess */
+  double t_other_ms;     /* projection, small dense, residuals, orthonormalisation */
+  double t_total_ms;
+  uint64_t bytes_resident; /* device bytes held by the solve at its peak */
+} rid_stats;
+
+/* ---- errors ---------------------------------------------------------- */
+RID_API const char* rid_status_string(rid_status s);
+/* Message of the last failing call on ctx (or of rid_context_create when
+ * ctx is NULL).  Valid until the next call on the same context. */
+RID_API const char* rid_last_error(const rid_context* ctx);
+
+/* ---- context ----------------------------------------------------------
+ * device: HIP device ordinal; hip_stream: a hipStream_t (NULL = the null
+ * stream); alloc: NULL = the library's own hipMalloc/hipFree. */
+RID_API rid_status rid_context_create(int32_t device, void* hip_stream, const rid_allocator* alloc,
+                              rid_context** out);
+RID_API rid_status rid_context_destroy(rid_context* ctx);
+
+/* ---- problem ----------------------------------------------------------
+ * Validates the descriptor, copies the orbital energies, computes the
+ * exchange window of Sec. 3.1 and makes the reduced-precision copies of the
+ * tensors that MIXED solves use (FP32 full tensor, BF16 ris tensor), charged
+ * to the allocator.  Borrowed tensors are never written. */
+RID_API rid_status rid_problem_create(rid_context* ctx, const rid_problem_desc* desc, rid_problem** out);
+RID_API rid_status rid_problem_destroy(rid_problem* prob);
+/* Bytes the problem holds on the device (cast copies and constants). */
+RID_API rid_status rid_problem_footprint(const rid_problem* prob, uint64_t* bytes);
+/* Active exchange window: occupied i >= *i0, virtual a < *nv_act. */
+RID_API rid_status rid_problem_window(const rid_problem* prob, int32_t* i0, int32_t* nv_act);
+
+RID_API void rid_solve_opts_default(rid_solve_opts* opts);
+
+/* ---- operator products (Eq. hessian; ris model of Sec. 2.2.2) --------
+ * y_dev (and y2_dev for the pair operators) = op applied to the nvec vectors
+ * x_dev (nvec x N, FP64).  precision: RID_F64 computes in FP64; RID_F32
+ * reads FP32 copies of tensor and vectors (FP64 reduction of partial sums);
+ * RID_BF16 (ris operators only) reads BF16 copies with FP32 accumulation.
+ * Outputs are FP64.  Synchronous. */
+RID_API rid_status rid_apply_operator(rid_problem* prob, int32_t op, int32_t precision, int32_t nvec,
+                              const double* x_dev, double* y_dev, double* y2_dev);
+
+/* ---- eigen-solve (Sec. 2.1; Eqs. TDA, Casida) ---------------------------
+ * The k lowest roots in ascending order into omega_host[k].  TDA: x_dev
+ * (k x N, optional) gets unit-norm eigenvectors.  RPA: x_dev and y_dev
+ * (optional) get X and Y with X^T X - Y^T Y = 1.  resid_host (optional, k)
+ * gets the final residual norms.  Returns RID_WARN_NOT_CONVERGED when
+ * max_iter is reached (outputs written), RID_ERR_INDEFINITE when the
+ * projected A-B is not positive definite, RID_ERR_BREAKDOWN when every new
+ * direction is dropped. */
+RID_API rid_status rid_eigen_solve(rid_problem* prob, const rid_solve_opts* opts, int32_t k, int32_t mode,
+                           double* omega_host, double* x_dev, double* y_dev, double* resid_host,
+                           rid_stats* stats);
+
+/* ---- polarizability (Eq. TDDFT_polar) -----------------------------------
+ * alpha_uv(w_f) = -2 P_u^T U_v(w_f), (A+B) U - w U' = -P, (A-B) U' - w U = 0,
+ * for p_dev (nrhs x N) and the nfreq frequencies omega_host (Hartree, >= 0).
+ * alpha_host: nfreq x nrhs x nrhs; u_dev (optional): nfreq x nrhs x N;
+ * resid_host (optional): nfreq x nrhs relative residuals.  Frequencies at or
+ * above 0.999 times the lowest diagonal element de_min give
+ * RID_ERR_NEAR_SINGULAR before any work is done. */
+RID_API rid_status rid_response_solve(rid_problem* prob, const rid_solve_opts* opts, int32_t nrhs,
+                              const double* p_dev, int32_t nfreq, const double* omega_host,
+                              double* alpha_host, double* u_dev, double* resid_host,
+                              rid_stats* stats);
+
+/* ---- batched solves (many molecules per launch) -------------------------
+ * A request is an eigen-solve (kind 0: k, mode) or a polarizability solve
+ * (kind 1: nrhs, p_dev, nfreq, omega_host).  Results are written into the
+ * caller-owned rid_result of each request. */
+typedef struct {
+  int32_t kind;            /* 0 = eigen, 1 = polarizability */
+  int32_t k, mode;         /* eigen */
+  int32_t nrhs, nfreq;     /* polarizability */
+  const double* p_dev;     /* nrhs x N */
+  const double* omega_host;/* nfreq */
+  rid_solve_opts opts;
+} rid_request;
+
+typedef struct {
+  rid_status status;
+  double* omega_host;      /* caller buffer: k (eigen) */
+  double* alpha_host;      /* caller buffer: nfreq*nrhs*nrhs (polarizability) */
+  double* resid_host;      /* caller buffer or NULL */
+  rid_stats stats;
+  double t_arrival_ms, t_admit_ms, t_done_ms; /* server timestamps */
+} rid_result;
+
+RID_API rid_status rid_batch_solve(rid_context* ctx, int32_t n, rid_problem* const* probs,
+                           const rid_request* reqs, rid_result* results);
+
+/* ---- continuous-batching server -----------------------------------------
+ * Requests are admitted while their device footprint fits hbm_budget_bytes
+ * and a slot is free; every engine tick advances every running request by one
+ * outer iteration.  States: queued -> running -> done / failed / cancelled. */
+typedef struct {
+  uint64_t hbm_budget_bytes;
+  int32_t max_slots;
+} rid_server_opts;
+
+RID_API rid_status rid_server_create(rid_context* ctx, const rid_server_opts* opts, rid_server** out);
+RID_API rid_status rid_server_submit(rid_server* srv, rid_problem* prob, const rid_request* req,
+                             rid_result* result, uint64_t* ticket);
+/* RID_OK when done (result written), RID_ERR_PENDING otherwise. */
+RID_API rid_status rid_server_poll(rid_server* srv, uint64_t ticket);
+RID_API rid_status rid_server_wait(rid_server* srv, uint64_t ticket, int32_t timeout_ms);
+RID_API rid_status rid_server_cancel(rid_server* srv, uint64_t ticket);
+RID_API rid_status rid_server_destroy(rid_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RID_H_ */

@@ -1,0 +1,157 @@
+"""ctypes mirror of include/rid.h: structures, constants and function prototypes.
+
+Argument marshalling only; every computation happens in librid.so.  Importing
+this module loads the library and raises ImportError when it is missing (there
+is no fallback path).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librid.so")
+
+RID_OK = 0
+RID_WARN_NOT_CONVERGED = 1
+RID_ERR_INVALID_ARG = -1
+RID_ERR_SHAPE = -2
+RID_ERR_DTYPE = -3
+RID_ERR_NO_MEMORY = -4
+RID_ERR_HIP = -5
+RID_ERR_INDEFINITE = -6
+RID_ERR_BREAKDOWN = -7
+RID_ERR_NEAR_SINGULAR = -8
+RID_ERR_NO_DEVICE = -9
+RID_ERR_INTERNAL = -10
+RID_ERR_CANCELLED = -11
+RID_ERR_TIMEOUT = -12
+RID_ERR_PENDING = -13
+
+RID_F64, RID_F32, RID_BF16 = 0, 1, 2
+RID_PRECOND_DIAG, RID_PRECOND_RIS = 0, 1
+RID_PRECISION_FP64, RID_PRECISION_MIXED = 0, 1
+RID_TDA, RID_RPA = 0, 1
+RID_OP_A, RID_OP_APB_AMB, RID_OP_T, RID_OP_TPM = 0, 1, 2, 3
+RID_MAX_HISTORY = 128
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class rid_allocator(ctypes.Structure):
+    _fields_ = [("user", ctypes.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
+class rid_problem_desc(ctypes.Structure):
+    _fields_ = [
+        ("no", ctypes.c_int32), ("nv", ctypes.c_int32), ("naux", ctypes.c_int32),
+        ("naux_ris", ctypes.c_int32), ("naux_ris_k", ctypes.c_int32),
+        ("a_x", ctypes.c_double), ("t_cut_ha", ctypes.c_double),
+        ("eps_occ_host", ctypes.POINTER(ctypes.c_double)),
+        ("eps_vir_host", ctypes.POINTER(ctypes.c_double)),
+        ("b_ia_dev", ctypes.c_void_p), ("b_ij_dev", ctypes.c_void_p), ("b_ab_dev", ctypes.c_void_p),
+        ("b_dtype", ctypes.c_int32),
+        ("bris_ia_dev", ctypes.c_void_p), ("bris_ij_dev", ctypes.c_void_p), ("bris_ab_dev", ctypes.c_void_p),
+        ("bris_dtype", ctypes.c_int32),
+    ]
+
+
+class rid_solve_opts(ctypes.Structure):
+    _fields_ = [
+        ("precond", ctypes.c_int32), ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32), ("n_extra_init", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+        ("inner_max_iter", ctypes.c_int32), ("init_tol", ctypes.c_double), ("init_max_iter", ctypes.c_int32),
+        ("m_max", ctypes.c_int32),
+    ]
+
+
+class rid_stats(ctypes.Structure):
+    _fields_ = [
+        ("n_iter", ctypes.c_int32), ("n_mv", ctypes.c_int32), ("n_inner_mv", ctypes.c_int32),
+        ("n_inner_iter", ctypes.c_int32), ("n_history", ctypes.c_int32),
+        ("history", ctypes.c_double * RID_MAX_HISTORY),
+        ("t_matvec_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
+        ("t_other_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+        ("bytes_resident", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return dict(n_iter=self.n_iter, n_mv=self.n_mv, n_inner_mv=self.n_inner_mv,
+                    n_inner_iter=self.n_inner_iter,
+                    history=[self.history[i] for i in range(self.n_history)],
+                    t_matvec_ms=self.t_matvec_ms, t_precond_ms=self.t_precond_ms,
+                    t_other_ms=self.t_other_ms, t_total_ms=self.t_total_ms,
+                    bytes_resident=int(self.bytes_resident))
+
+
+class rid_request(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("nrhs", ctypes.c_int32), ("nfreq", ctypes.c_int32),
+        ("p_dev", ctypes.c_void_p), ("omega_host", ctypes.POINTER(ctypes.c_double)),
+        ("opts", rid_solve_opts),
+    ]
+
+
+class rid_result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("omega_host", ctypes.POINTER(ctypes.c_double)),
+        ("alpha_host", ctypes.POINTER(ctypes.c_double)),
+        ("resid_host", ctypes.POINTER(ctypes.c_double)),
+        ("stats", rid_stats),
+        ("t_arrival_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+    ]
+
+
+class rid_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32)]
+
+
+P = ctypes.c_void_p
+PP = ctypes.POINTER(ctypes.c_void_p)
+DP = ctypes.POINTER(ctypes.c_double)
+I32 = ctypes.c_int32
+
+# name: (restype, argtypes) -- one entry per function declared in include/rid.h
+PROTOTYPES = {
+    "rid_status_string": (ctypes.c_char_p, [I32]),
+    "rid_last_error": (ctypes.c_char_p, [P]),
+    "rid_context_create": (I32, [I32, P, ctypes.POINTER(rid_allocator), PP]),
+    "rid_context_destroy": (I32, [P]),
+    "rid_problem_create": (I32, [P, ctypes.POINTER(rid_problem_desc), PP]),
+    "rid_problem_destroy": (I32, [P]),
+    "rid_problem_footprint": (I32, [P, ctypes.POINTER(ctypes.c_uint64)]),
+    "rid_problem_window": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+    "rid_solve_opts_default": (None, [ctypes.POINTER(rid_solve_opts)]),
+    "rid_apply_operator": (I32, [P, I32, I32, I32, P, P, P]),
+    "rid_eigen_solve": (I32, [P, ctypes.POINTER(rid_solve_opts), I32, I32, DP, P, P, DP,
+                              ctypes.POINTER(rid_stats)]),
+    "rid_response_solve": (I32, [P, ctypes.POINTER(rid_solve_opts), I32, P, I32, DP, DP, P, DP,
+                                 ctypes.POINTER(rid_stats)]),
+    "rid_batch_solve": (I32, [P, I32, PP, ctypes.POINTER(rid_request), ctypes.POINTER(rid_result)]),
+    "rid_server_create": (I32, [P, ctypes.POINTER(rid_server_opts), PP]),
+    "rid_server_submit": (I32, [P, P, ctypes.POINTER(rid_request), ctypes.POINTER(rid_result),
+                                ctypes.POINTER(ctypes.c_uint64)]),
+    "rid_server_poll": (I32, [P, ctypes.c_uint64]),
+    "rid_server_wait": (I32, [P, ctypes.c_uint64, I32]),
+    "rid_server_cancel": (I32, [P, ctypes.c_uint64]),
+    "rid_server_destroy": (I32, [P]),
+}
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError("librid.so is not built (%s); run `python -m paper_2404_17133_amd.build` "
+                          "or __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in PROTOTYPES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = load()

@@ -1,0 +1,28 @@
+// Krylov solvers of the library (see engine.hip).
+#pragma once
+
+#include <vector>
+
+#include "core.hpp"
+
+namespace rid {
+
+struct SolveStats {
+  int n_iter = 0, n_mv = 0, n_inner_mv = 0, n_inner_iter = 0;
+  std::vector<double> history;
+  double t_matvec = 0.0, t_precond = 0.0, t_other = 0.0, t_total = 0.0;  // ms
+  uint64_t peak_bytes = 0;
+};
+
+// k lowest roots; TDA (mode 0) or full TDDFT (mode 1).  Returns RID_OK,
+// RID_WARN_NOT_CONVERGED or throws rid::Error.
+rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode, double* omega_host, double* x_dev,
+                       double* y_dev, double* resid_host, SolveStats& st);
+
+rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, const double* p_dev, int nfreq,
+                          const double* omega_host, double* alpha_host, double* u_dev, double* resid_host,
+                          SolveStats& st);
+
+void validate_opts(const rid_solve_opts& o, const rid_problem* P);
+
+}  // namespace rid

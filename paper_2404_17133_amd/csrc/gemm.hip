@@ -1,0 +1,317 @@
+// MFMA GEMM kernels for gfx950 (see gemm.hpp for the operation).
+//
+// Tiling: a workgroup of 4 waves owns a BM x BN output tile; each wave owns a
+// WM x WN sub-tile made of MFMA atoms (32x32 for f32/bf16, 16x16 for f64).
+// Every K stage moves 128 bytes of K per operand row (32 f32, 16 f64, 64
+// bf16) from global memory to LDS, double-buffered with one barrier per
+// stage: the next stage's global loads are issued before the current stage's
+// MFMAs and written to the other LDS buffer afterwards.  LDS rows are padded
+// by 16 bytes (stride 144 B) so that the 16-byte fragment reads of 16
+// consecutive rows hit distinct banks.  The K order inside a stage is
+// permuted so that each lane reads one contiguous slice per operand row: lane
+// group g (lanes sharing a row) takes the g-th slice of the stage, and MFMA
+// step s consumes the s-th element(s) of every group's slice.  Since A and B
+// use the same permutation the sum over K is unchanged.
+#include "gemm.hpp"
+
+namespace rid {
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+template <typename T>
+struct Atom;
+
+// v_mfma_f64_16x16x4_f64: A lane l holds A[l%16][k-group l/16]; D lane l,
+// register r holds D[l/16 + 4*r][l%16] (rows interleaved across the four
+// lane groups, unlike the FP32 16x16 layout; measured on gfx950).
+template <>
+struct Atom<double> {
+  typedef double elem_t;
+  typedef double acc_t;
+  typedef v4d accv_t;
+  typedef v2d vec_t;
+  static constexpr int AM = 16, G = 4, E = 1, NACC = 4;
+  __device__ static inline double op(const vec_t* f, int s) { return f[s >> 1][s & 1]; }
+  __device__ static inline accv_t mma(double a, double b, accv_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  __device__ static inline double out(acc_t v) { return v; }
+};
+
+// v_mfma_f32_32x32x2_f32: A lane l holds A[l%32][k-group l/32]; D lane l,
+// register r holds D[(r/4)*8 + (l/32)*4 + r%4][l%32].
+template <>
+struct Atom<float> {
+  typedef float elem_t;
+  typedef float acc_t;
+  typedef v16f accv_t;
+  typedef v4f vec_t;
+  static constexpr int AM = 32, G = 2, E = 1, NACC = 16;
+  __device__ static inline float op(const vec_t* f, int s) { return f[s >> 2][s & 3]; }
+  __device__ static inline accv_t mma(float a, float b, accv_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int r) { return (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3); }
+  __device__ static inline float out(acc_t v) { return v; }
+};
+
+// v_mfma_f32_32x32x16_bf16: A lane l holds 8 consecutive K of row l%32 in
+// k-group l/32; D layout as for the f32 32x32 atom.
+template <>
+struct Atom<bf16_t> {
+  typedef uint16_t elem_t;
+  typedef float acc_t;
+  typedef v16f accv_t;
+  typedef v8bf vec_t;
+  static constexpr int AM = 32, G = 2, E = 8, NACC = 16;
+  __device__ static inline v8bf op(const vec_t* f, int s) { return f[s]; }
+  __device__ static inline accv_t mma(v8bf a, v8bf b, accv_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int r) { return (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3); }
+  __device__ static inline uint16_t out(acc_t v) { return f32_to_bf16_bits(v); }
+};
+
+template <typename T, int BM, int BN, int WM, int WN, bool VEC>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmParams p) {
+  using At = Atom<T>;
+  using E_t = typename At::elem_t;
+  using V_t = typename At::vec_t;
+  using acc_t = typename At::acc_t;
+  using accv_t = typename At::accv_t;
+  constexpr int VW = 16 / (int)sizeof(E_t);  // elements per 16-byte chunk
+  constexpr int BK = 8 * VW;                 // 128 bytes of K per stage
+  constexpr int RS = 9;                      // LDS row stride in 16-byte chunks
+  constexpr int ROWS = BM + BN;
+  constexpr int CPT = ROWS * 8 / 256;        // chunks per thread per stage
+  static_assert((ROWS * 8) % 256 == 0, "tile rows must be a multiple of 32");
+  constexpr int NWM = BM / WM;
+  constexpr int NWN = BN / WN;
+  static_assert(NWM * NWN == 4, "four waves per workgroup");
+  constexpr int AMN = WM / At::AM;
+  constexpr int ANN = WN / At::AM;
+  constexpr int SL = 8 / At::G;              // chunks per lane slice
+  constexpr int KSTEPS = BK / At::G / At::E; // MFMA steps per stage
+
+  __shared__ uint4 lds[2][ROWS * RS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tiles_m = (p.M + BM - 1) / BM;
+  const int tm = blockIdx.x % tiles_m;
+  const int tn = blockIdx.x / tiles_m;
+  const int m0 = tm * BM;
+  const int n0 = tn * BN;
+  const int z = blockIdx.y;
+  const int z1 = z / p.nz2, z2 = z % p.nz2;
+  const int split = blockIdx.z;
+  const int pbeg = split * p.pps;
+  const int pend = min(p.np, pbeg + p.pps);
+  const E_t* Ab = reinterpret_cast<const E_t*>(p.A) + z1 * p.sA1 + z2 * p.sA2;
+  const E_t* Bb = reinterpret_cast<const E_t*>(p.B) + z1 * p.sB1 + z2 * p.sB2;
+  const int nkt = (p.K + BK - 1) / BK;
+  const int nstage = pend > pbeg ? (pend - pbeg) * nkt : 0;
+
+  const int kc = tid & 7;
+  const int rbase = tid >> 3;
+  uint4 pre[CPT];
+
+  auto gload = [&](int t) {
+    const int pp = pbeg + t / nkt;
+    const int k = (t % nkt) * BK + kc * VW;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int r = rbase + 32 * i;
+      const E_t* src;
+      bool ok;
+      if (r < BM) {
+        const int m = m0 + r;
+        ok = m < p.M;
+        src = Ab + pp * p.sAp + (long)m * p.lda + k;
+      } else {
+        const int n = n0 + (r - BM);
+        ok = n < p.N;
+        src = Bb + pp * p.sBp + (long)n * p.ldb + k;
+      }
+      if constexpr (VEC) {
+        pre[i] = (ok && k < p.K) ? *reinterpret_cast<const uint4*>(src) : make_uint4(0, 0, 0, 0);
+      } else {
+        union { uint4 v; E_t e[VW]; } u;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) u.e[e] = (ok && k + e < p.K) ? src[e] : E_t(0);
+        pre[i] = u.v;
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) lds[buf][(rbase + 32 * i) * RS + kc] = pre[i];
+  };
+
+  const int wm = (wave % NWM) * WM;
+  const int wn = (wave / NWM) * WN;
+  const int lr = lane % At::AM;
+  const int g = lane / At::AM;
+
+  accv_t acc[AMN][ANN];
+#pragma unroll
+  for (int i = 0; i < AMN; ++i)
+#pragma unroll
+    for (int j = 0; j < ANN; ++j)
+#pragma unroll
+      for (int r = 0; r < At::NACC; ++r) acc[i][j][r] = acc_t(0);
+
+  if (nstage > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int t = 0; t < nstage; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < nstage) gload(t + 1);
+    V_t fa[AMN][SL];
+    V_t fb[ANN][SL];
+#pragma unroll
+    for (int i = 0; i < AMN; ++i) {
+      const uint4* src = &lds[buf][(wm + i * At::AM + lr) * RS + g * SL];
+#pragma unroll
+      for (int c = 0; c < SL; ++c) fa[i][c] = *reinterpret_cast<const V_t*>(src + c);
+    }
+#pragma unroll
+    for (int j = 0; j < ANN; ++j) {
+      const uint4* src = &lds[buf][(BM + wn + j * At::AM + lr) * RS + g * SL];
+#pragma unroll
+      for (int c = 0; c < SL; ++c) fb[j][c] = *reinterpret_cast<const V_t*>(src + c);
+    }
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s)
+#pragma unroll
+      for (int i = 0; i < AMN; ++i)
+#pragma unroll
+        for (int j = 0; j < ANN; ++j) acc[i][j] = At::mma(At::op(fa[i], s), At::op(fb[j], s), acc[i][j]);
+    if (t + 1 < nstage) lstore((t + 1) & 1);
+    __syncthreads();
+  }
+
+  // epilogue
+  const acc_t alpha = (acc_t)p.alpha;
+  if (p.mode == GEMM_STORE) {
+    E_t* C = reinterpret_cast<E_t*>(p.C) + z1 * p.sC1 + z2 * p.sC2;
+#pragma unroll
+    for (int i = 0; i < AMN; ++i)
+#pragma unroll
+      for (int j = 0; j < ANN; ++j)
+#pragma unroll
+        for (int r = 0; r < At::NACC; ++r) {
+          const int m = m0 + wm + i * At::AM + At::row(lane, r);
+          const int n = n0 + wn + j * At::AM + lr;
+          if (m < p.M && n < p.N) C[(long)m * p.ldc + n] = At::out(alpha * acc[i][j][r]);
+        }
+  } else {
+    acc_t* C = reinterpret_cast<acc_t*>(p.C) + split * p.sCs + z1 * p.sC1 + z2 * p.sC2;
+    const bool add = p.mode == GEMM_PARTIAL_ADD;
+#pragma unroll
+    for (int i = 0; i < AMN; ++i)
+#pragma unroll
+      for (int j = 0; j < ANN; ++j)
+#pragma unroll
+        for (int r = 0; r < At::NACC; ++r) {
+          const int m = m0 + wm + i * At::AM + At::row(lane, r);
+          const int n = n0 + wn + j * At::AM + lr;
+          if (m < p.M && n < p.N) {
+            acc_t* dst = C + (long)m * p.ldc + n;
+            const acc_t v = alpha * acc[i][j][r];
+            *dst = add ? *dst + v : v;
+          }
+        }
+  }
+}
+
+struct TileCfg {
+  int bm, bn;
+};
+
+template <typename T>
+struct Cfgs;
+template <>
+struct Cfgs<double> {
+  static constexpr TileCfg c[3] = {{128, 128}, {64, 64}, {128, 64}};
+};
+template <>
+struct Cfgs<float> {
+  static constexpr TileCfg c[3] = {{128, 128}, {64, 64}, {128, 64}};
+};
+template <>
+struct Cfgs<bf16_t> {
+  static constexpr TileCfg c[3] = {{128, 128}, {64, 64}, {128, 64}};
+};
+
+template <typename T, int BM, int BN, int WM, int WN>
+void launch_cfg(const GemmParams& p, int nz, int nsplit, bool vec, hipStream_t stream) {
+  const int tiles = ceil_div(p.M, BM) * ceil_div(p.N, BN);
+  dim3 grid(tiles, nz, nsplit);
+  if (vec)
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, true>), grid, dim3(256), 0, stream, p);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, false>), grid, dim3(256), 0, stream, p);
+}
+
+template <typename T>
+int elem_size() {
+  return std::is_same<T, bf16_t>::value ? 2 : (int)sizeof(T);
+}
+
+}  // namespace
+
+template <typename T>
+int gemm_num_configs() {
+  return 3;
+}
+template <typename T>
+void gemm_config_tile(int cfg, int* bm, int* bn) {
+  *bm = Cfgs<T>::c[cfg].bm;
+  *bn = Cfgs<T>::c[cfg].bn;
+}
+
+template <typename T>
+void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int cfg) {
+  if (p.M <= 0 || p.N <= 0 || nz <= 0 || nsplit <= 0) return;
+  RID_CHECK(p.np >= 1 && p.pps >= 1 && p.nz2 >= 1, RID_ERR_INTERNAL, "gemm: bad batch counts");
+  RID_CHECK((long)nsplit * p.pps >= p.np, RID_ERR_INTERNAL, "gemm: splits do not cover batches");
+  RID_CHECK(ceil_div_l(p.M, 64) * ceil_div_l(p.N, 64) < (1L << 31), RID_ERR_SHAPE, "gemm: grid too large");
+  RID_CHECK(nz < 65536 && nsplit < 65536, RID_ERR_SHAPE, "gemm: batch grid too large");
+  const int vw = 16 / elem_size<T>();
+  const bool vec = (p.K % vw == 0) && (p.lda % vw == 0) && (p.ldb % vw == 0) && (p.sAp % vw == 0) &&
+                   (p.sBp % vw == 0) && (p.sA1 % vw == 0) && (p.sA2 % vw == 0) && (p.sB1 % vw == 0) &&
+                   (p.sB2 % vw == 0) && ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.B % 16 == 0);
+  if (cfg < 0) {
+    // default: big tiles when the output is large enough to fill the chip
+    const long t128 = ceil_div_l(p.M, 128) * ceil_div_l(p.N, 128) * (long)nz * nsplit;
+    cfg = (t128 >= 512) ? 0 : 1;
+  }
+  switch (cfg) {
+    case 0: launch_cfg<T, 128, 128, 64, 64>(p, nz, nsplit, vec, stream); break;
+    case 1: launch_cfg<T, 64, 64, 32, 32>(p, nz, nsplit, vec, stream); break;
+    default: launch_cfg<T, 128, 64, 64, 32>(p, nz, nsplit, vec, stream); break;
+  }
+  RID_HIP(hipGetLastError());
+}
+
+template void gemm_nt<double>(const GemmParams&, int, int, hipStream_t, int);
+template void gemm_nt<float>(const GemmParams&, int, int, hipStream_t, int);
+template void gemm_nt<bf16_t>(const GemmParams&, int, int, hipStream_t, int);
+template int gemm_num_configs<double>();
+template int gemm_num_configs<float>();
+template int gemm_num_configs<bf16_t>();
+template void gemm_config_tile<double>(int, int*, int*);
+template void gemm_config_tile<float>(int, int*, int*);
+template void gemm_config_tile<bf16_t>(int, int*, int*);
+
+}  // namespace rid

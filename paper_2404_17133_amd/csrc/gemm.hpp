@@ -1,0 +1,50 @@
+// Batched, reduction-batched MFMA GEMM for gfx950:
+//
+//   C[z](m, n) (=|+=) alpha * sum_{p in split} sum_k A[z, p](m, k) * B[z, p](n, k)
+//
+// Both operands are K-contiguous ("NT"): A(m, k) at A + off_A(z, p) + m*lda + k,
+// B(n, k) at B + off_B(z, p) + n*ldb + k.  z = blockIdx.y is split into
+// (z1, z2) = (z / nz2, z % nz2) with independent strides, p runs over the
+// reduction batches assigned to split s = blockIdx.z.  Element types:
+// double (v_mfma_f64_16x16x4), float (v_mfma_f32_32x32x2), bf16 stored as
+// uint16_t (v_mfma_f32_32x32x16_bf16, FP32 accumulation).
+#pragma once
+
+#include "common.hpp"
+
+namespace rid {
+
+enum GemmMode { GEMM_STORE = 0, GEMM_PARTIAL_SET = 1, GEMM_PARTIAL_ADD = 2 };
+
+struct GemmParams {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K;
+  int np;    // reduction batches in total
+  int pps;   // reduction batches per split
+  int nz2;   // inner z extent
+  long lda, ldb, ldc;
+  long sAp, sBp;
+  long sA1, sA2, sB1, sB2, sC1, sC2;
+  long sCs;  // stride between split outputs (partial modes)
+  double alpha;
+  int mode;  // GemmMode
+};
+
+// Element-type tag for bf16 operands stored as raw uint16_t.
+struct bf16_t {};
+
+// Launch one GEMM.  T = double, float or bf16_t.  For the partial modes the
+// output is written in the accumulator type (double for T = double, float
+// otherwise); for GEMM_STORE it is written in T.
+template <typename T>
+void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int tile_cfg = -1);
+
+// Number of tile configurations available for T (for the autotuner).
+template <typename T>
+int gemm_num_configs();
+template <typename T>
+void gemm_config_tile(int cfg, int* bm, int* bn);
+
+}  // namespace rid

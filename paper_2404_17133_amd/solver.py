@@ -1,0 +1,345 @@
+"""Thin Python front end of librid.so (argument marshalling only).
+
+PyTorch provides device memory (through the allocator callbacks) and the HIP
+stream; every step of every solve runs in the library's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import weakref
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _binding as B
+
+_PRECOND = {"diag": B.RID_PRECOND_DIAG, "ris": B.RID_PRECOND_RIS}
+_PRECISION = {"fp64": B.RID_PRECISION_FP64, "mixed": B.RID_PRECISION_MIXED}
+_MODE = {"tda": B.RID_TDA, "rpa": B.RID_RPA}
+_OPS = {"A": B.RID_OP_A, "APB_AMB": B.RID_OP_APB_AMB, "T": B.RID_OP_T, "TPM": B.RID_OP_TPM}
+_DTYPES = {"f64": B.RID_F64, "f32": B.RID_F32, "bf16": B.RID_BF16}
+
+
+class RidError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (status %d): %s" % (B.lib.rid_status_string(status).decode(), status, message))
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _need_dev(t: torch.Tensor, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError("%s must be a float64 CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+
+class Context:
+    """A device, a stream and a PyTorch-backed device allocator."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, torch_allocator: bool = True):
+        self.device = device
+        self.stream = stream or torch.cuda.current_stream(device)
+        self._children = weakref.WeakSet()  # problems and servers, closed before the context
+        blocks = {}
+        self._blocks = blocks
+        self._alloc_ref = None
+        alloc = None
+        if torch_allocator:
+            dev = torch.device("cuda", device)
+
+            # the callbacks hold the block table, not the context, so that no
+            # reference cycle decides the order of finalisation
+            def _alloc(user, nbytes):
+                try:
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+                except Exception:  # out of memory: the library reports RID_ERR_NO_MEMORY
+                    return None
+                blocks[t.data_ptr()] = t
+                return t.data_ptr()
+
+            def _free(user, p):
+                blocks.pop(int(p) if p else 0, None)
+
+            self._alloc_ref = (B.ALLOC_FN(_alloc), B.FREE_FN(_free))
+            alloc = B.rid_allocator(None, self._alloc_ref[0], self._alloc_ref[1])
+        h = ctypes.c_void_p()
+        s = B.lib.rid_context_create(device, ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(alloc) if alloc is not None else None, ctypes.byref(h))
+        if s != B.RID_OK:
+            raise RidError(s, B.lib.rid_last_error(None).decode())
+        self.handle = h
+
+    def check(self, s: int, ok=(B.RID_OK,)):
+        if s not in ok:
+            raise RidError(s, B.lib.rid_last_error(self.handle).decode())
+        return s
+
+    def close(self):
+        if getattr(self, "handle", None):
+            for ch in list(self._children):
+                ch.close()
+            B.lib.rid_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_opts(precond: str = "ris", precision: str = "fp64", **kw) -> B.rid_solve_opts:
+    o = B.rid_solve_opts()
+    B.lib.rid_solve_opts_default(ctypes.byref(o))
+    o.precond = _PRECOND[precond]
+    o.precision = _PRECISION[precision]
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """One molecule: orbital energies and borrowed FP64 device tensors."""
+
+    def __init__(self, ctx: Context, eps_occ, eps_vir, b_ia, b_ij, b_ab, a_x: float,
+                 bris_ia=None, bris_ij=None, bris_ab=None, naux_ris_k: int = 0, t_cut: float = 0.0):
+        self.ctx = ctx
+        self.eps_occ = np.ascontiguousarray(np.asarray(eps_occ, dtype=np.float64))
+        self.eps_vir = np.ascontiguousarray(np.asarray(eps_vir, dtype=np.float64))
+        no, nv = len(self.eps_occ), len(self.eps_vir)
+        naux = b_ia.shape[0]
+        _need_dev(b_ia, (naux, no, nv), "b_ia")
+        _need_dev(b_ij, (naux, no, no), "b_ij")
+        _need_dev(b_ab, (naux, nv, nv), "b_ab")
+        nris = 0
+        if bris_ia is not None:
+            nris = bris_ia.shape[0]
+            _need_dev(bris_ia, (nris, no, nv), "bris_ia")
+            _need_dev(bris_ij, (nris, no, no), "bris_ij")
+            _need_dev(bris_ab, (nris, nv, nv), "bris_ab")
+        self.no, self.nv, self.naux, self.naux_ris = no, nv, naux, nris
+        self.n = no * nv
+        self._keep = (b_ia, b_ij, b_ab, bris_ia, bris_ij, bris_ab)
+        d = B.rid_problem_desc()
+        d.no, d.nv, d.naux, d.naux_ris, d.naux_ris_k = no, nv, naux, nris, naux_ris_k
+        d.a_x = a_x
+        d.t_cut_ha = t_cut if np.isfinite(t_cut) else 0.0
+        d.eps_occ_host = _dptr(self.eps_occ)
+        d.eps_vir_host = _dptr(self.eps_vir)
+        d.b_ia_dev, d.b_ij_dev, d.b_ab_dev = b_ia.data_ptr(), b_ij.data_ptr(), b_ab.data_ptr()
+        d.b_dtype = B.RID_F64
+        if nris:
+            d.bris_ia_dev, d.bris_ij_dev, d.bris_ab_dev = bris_ia.data_ptr(), bris_ij.data_ptr(), bris_ab.data_ptr()
+        d.bris_dtype = B.RID_F64
+        h = ctypes.c_void_p()
+        ctx.check(B.lib.rid_problem_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+        ctx._children.add(self)
+
+    @classmethod
+    def from_synth(cls, ctx: Context, p) -> "Problem":
+        """From a synth.Problem whose tensors live on the context's device."""
+        return cls(ctx, p.eps_occ.cpu().numpy(), p.eps_vir.cpu().numpy(), p.b_ia, p.b_ij, p.b_ab, p.a_x,
+                   p.bris_ia, p.bris_ij, p.bris_ab, p.naux_ris_k, p.t_cut)
+
+    def window(self):
+        i0, na = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx.check(B.lib.rid_problem_window(self.handle, ctypes.byref(i0), ctypes.byref(na)))
+        return i0.value, na.value
+
+    def footprint(self) -> int:
+        b = ctypes.c_uint64()
+        self.ctx.check(B.lib.rid_problem_footprint(self.handle, ctypes.byref(b)))
+        return int(b.value)
+
+    def apply(self, op: str, x: torch.Tensor, dtype: str = "f64"):
+        """op(x) for x (nvec, N) float64 on the device; returns y or (y, y2)."""
+        _need_dev(x, None, "x")
+        nvec = x.shape[0]
+        if x.shape[1] != self.n:
+            raise ValueError("x must have N = no*nv columns")
+        y = torch.empty_like(x)
+        pair = op in ("APB_AMB", "TPM")
+        y2 = torch.empty_like(x) if pair else None
+        self.ctx.check(B.lib.rid_apply_operator(self.handle, _OPS[op], _DTYPES[dtype], nvec, _ptr(x), _ptr(y),
+                                                _ptr(y2)))
+        return (y, y2) if pair else y
+
+    def eigen(self, k: int, mode: str = "tda", precond: str = "ris", precision: str = "fp64",
+              vectors: bool = True, **kw):
+        """k lowest roots.  Returns dict(omega, resid, x, y, stats, status)."""
+        o = default_opts(precond, precision, **kw)
+        om = np.zeros(k)
+        rs = np.zeros(k)
+        x = torch.empty((k, self.n), dtype=torch.float64, device=self.b_device) if vectors else None
+        y = torch.empty((k, self.n), dtype=torch.float64, device=self.b_device) if (vectors and mode == "rpa") else None
+        st = B.rid_stats()
+        s = self.ctx.check(B.lib.rid_eigen_solve(self.handle, ctypes.byref(o), k, _MODE[mode], _dptr(om), _ptr(x),
+                                                 _ptr(y), _dptr(rs), ctypes.byref(st)),
+                           ok=(B.RID_OK, B.RID_WARN_NOT_CONVERGED))
+        return dict(omega=om, resid=rs, x=x, y=y, stats=st.as_dict(), status=s)
+
+    def polarizability(self, p: torch.Tensor, omegas: Sequence[float], precond: str = "ris",
+                       precision: str = "fp64", vectors: bool = False, **kw):
+        """alpha[f, u, v] for right-hand sides p (nrhs, N).  Returns dict."""
+        _need_dev(p, None, "p")
+        nrhs = p.shape[0]
+        om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+        nf = len(om)
+        o = default_opts(precond, precision, **kw)
+        alpha = np.zeros((nf, nrhs, nrhs))
+        rs = np.zeros((nf, nrhs))
+        u = torch.empty((nf, nrhs, self.n), dtype=torch.float64, device=self.b_device) if vectors else None
+        st = B.rid_stats()
+        s = self.ctx.check(B.lib.rid_response_solve(self.handle, ctypes.byref(o), nrhs, _ptr(p), nf, _dptr(om),
+                                                    _dptr(alpha), _ptr(u), _dptr(rs), ctypes.byref(st)),
+                           ok=(B.RID_OK, B.RID_WARN_NOT_CONVERGED))
+        return dict(alpha=alpha, resid=rs, u=u, stats=st.as_dict(), status=s)
+
+    @property
+    def b_device(self):
+        return self._keep[0].device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            if getattr(self.ctx, "handle", None):
+                B.lib.rid_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_request(kind: str, opts: B.rid_solve_opts, k: int = 0, mode: str = "tda",
+                 p: Optional[torch.Tensor] = None, omegas: Optional[np.ndarray] = None):
+    r = B.rid_request()
+    r.opts = opts
+    keep = []
+    if kind == "eigen":
+        r.kind, r.k, r.mode = 0, k, _MODE[mode]
+    else:
+        r.kind = 1
+        om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+        keep.append(om)
+        r.nrhs, r.nfreq = p.shape[0], len(om)
+        r.p_dev = p.data_ptr()
+        r.omega_host = _dptr(om)
+        keep.append(p)
+    return r, keep
+
+
+def make_result(req: B.rid_request):
+    res = B.rid_result()
+    keep = {}
+    if req.kind == 0:
+        keep["omega"] = np.zeros(req.k)
+        keep["resid"] = np.zeros(req.k)
+    else:
+        keep["alpha"] = np.zeros((req.nfreq, req.nrhs, req.nrhs))
+        keep["resid"] = np.zeros((req.nfreq, req.nrhs))
+        res.alpha_host = _dptr(keep["alpha"])
+    if "omega" in keep:
+        res.omega_host = _dptr(keep["omega"])
+    res.resid_host = _dptr(keep["resid"])
+    return res, keep
+
+
+def batch_solve(ctx: Context, problems: Sequence[Problem], requests: Sequence[B.rid_request]):
+    n = len(problems)
+    hp = (ctypes.c_void_p * n)(*[p.handle.value for p in problems])
+    rq = (B.rid_request * n)(*requests)
+    results, keeps = [], []
+    for r in requests:
+        res, keep = make_result(r)
+        results.append(res)
+        keeps.append(keep)
+    rs = (B.rid_result * n)(*results)
+    # the arrays above copied the structs: point the copies at the kept buffers
+    for i in range(n):
+        k = keeps[i]
+        if "omega" in k:
+            rs[i].omega_host = _dptr(k["omega"])
+        if "alpha" in k:
+            rs[i].alpha_host = _dptr(k["alpha"])
+        rs[i].resid_host = _dptr(k["resid"])
+    s = B.lib.rid_batch_solve(ctx.handle, n, ctypes.cast(hp, ctypes.POINTER(ctypes.c_void_p)), rq, rs)
+    out = []
+    for i in range(n):
+        d = dict(keeps[i])
+        d["status"] = rs[i].status
+        d["stats"] = rs[i].stats.as_dict()
+        out.append(d)
+    return s, out
+
+
+class Server:
+    """Continuous-batching request server."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int, max_slots: int):
+        self.ctx = ctx
+        o = B.rid_server_opts(hbm_budget_bytes, max_slots)
+        h = ctypes.c_void_p()
+        ctx.check(B.lib.rid_server_create(ctx.handle, ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self._live = {}
+        ctx._children.add(self)
+
+    def submit(self, prob: Problem, req: B.rid_request, keep=()) -> int:
+        res, bufs = make_result(req)
+        box = {"req": req, "res": res, "bufs": bufs, "keep": keep, "prob": prob}
+        t = ctypes.c_uint64()
+        self.ctx.check(B.lib.rid_server_submit(self.handle, prob.handle, ctypes.byref(box["req"]),
+                                               ctypes.byref(box["res"]), ctypes.byref(t)))
+        self._live[t.value] = box
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        s = B.lib.rid_server_poll(self.handle, ticket)
+        if s == B.RID_OK:
+            return True
+        if s == B.RID_ERR_PENDING:
+            return False
+        raise RidError(s, "poll failed")
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> dict:
+        s = B.lib.rid_server_wait(self.handle, ticket, timeout_ms)
+        if s != B.RID_OK:
+            raise RidError(s, "wait failed")
+        box = self._live[ticket]
+        res = box["res"]
+        d = dict(box["bufs"])
+        d.update(status=res.status, stats=res.stats.as_dict(), t_arrival_ms=res.t_arrival_ms,
+                 t_admit_ms=res.t_admit_ms, t_done_ms=res.t_done_ms)
+        return d
+
+    def cancel(self, ticket: int):
+        self.ctx.check(B.lib.rid_server_cancel(self.handle, ticket))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            if getattr(self.ctx, "handle", None):
+                B.lib.rid_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

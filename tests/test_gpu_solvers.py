@@ -1,0 +1,104 @@
+"""Solves through the C ABI against the FP64 oracle (GPU).
+
+The oracle runs at tolerance 1e-8 and is the truth.  Converged GPU roots
+must agree to 1e-6 Ha and polarizabilities to 1e-5 relative, in both the FP64
+and the mixed-precision paths.  Iteration counts are compared loosely: the
+GPU path reproduces the oracle's algorithm, but rounding differences (and the
+FP32/BF16 products of the mixed path) may shift a count by an iteration.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import OracleProblem, eigen_rpa, eigen_tda, polarizability
+from synth import make_dipoles, make_problem
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def config0():
+    if "c0" not in _CACHE:
+        p = make_problem(20, 80, 400, 90, seed=0)
+        op = OracleProblem.from_arrays(p.numpy())
+        _CACHE["c0"] = (p, op)
+    return _CACHE["c0"]
+
+
+def gpu_problem(p):
+    import paper_2404_17133_amd as rid
+
+    ctx = rid.Context(0)
+    return ctx, rid.Problem.from_synth(ctx, p.to("cuda:0"))
+
+
+@pytest.mark.parametrize("precond", ["diag", "ris"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tda_config0(precond, precision):
+    p, op = config0()
+    ref = eigen_tda(op, 5, "diag", tol=1e-8)
+    ref5 = eigen_tda(op, 5, precond, tol=1e-5)
+    ctx, prob = gpu_problem(p)
+    print("tda", precond, precision, flush=True)
+    out = prob.eigen(5, "tda", precond, precision)
+    assert out["status"] == 0
+    err = np.abs(out["omega"] - ref.omega).max()
+    assert err < 1e-6, err
+    assert np.all(out["resid"] < 1e-5)
+    # unit eigenvectors that match the oracle's up to sign
+    x = out["x"].cpu().numpy()
+    np.testing.assert_allclose(np.linalg.norm(x, axis=1), 1.0, atol=1e-10)
+    ov = np.abs(np.sum(x.T * ref.x, axis=0))
+    assert np.all(ov > 1 - 1e-6), ov
+    if precision == "fp64":
+        assert abs(out["stats"]["n_iter"] - ref5.n_iter) <= 1, (out["stats"]["n_iter"], ref5.n_iter)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precond", ["diag", "ris"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_rpa_config0(precond, precision):
+    p, op = config0()
+    ref = eigen_rpa(op, 5, "diag", tol=1e-8)
+    ctx, prob = gpu_problem(p)
+    print("rpa", precond, precision, flush=True)
+    out = prob.eigen(5, "rpa", precond, precision)
+    assert out["status"] == 0
+    err = np.abs(out["omega"] - ref.omega).max()
+    assert err < 1e-6, err
+    x, y = out["x"].cpu().numpy(), out["y"].cpu().numpy()
+    np.testing.assert_allclose(np.sum(x * x, axis=1) - np.sum(y * y, axis=1), 1.0, atol=1e-8)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precond", ["diag", "ris"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_polarizability_config0(precond, precision):
+    p, op = config0()
+    pm = make_dipoles(p, 3)
+    om = [0.0, 0.0569542, 0.2]
+    ref = polarizability(op, pm.numpy().T, om, "diag", tol=1e-8)
+    ctx, prob = gpu_problem(p)
+    print("alpha", precond, precision, flush=True)
+    out = prob.polarizability(pm.to("cuda:0").contiguous(), om, precond, precision)
+    assert out["status"] == 0
+    rel = np.abs(out["alpha"] - ref.alpha).max() / np.abs(ref.alpha).max()
+    assert rel < 1e-5, rel
+    ctx.close()
+
+
+def test_not_converged_and_near_singular():
+    import paper_2404_17133_amd as rid
+
+    p, op = config0()
+    ctx, prob = gpu_problem(p)
+    out = prob.eigen(5, "tda", "diag", "fp64", max_iter=1)
+    assert out["status"] == 1 and out["stats"]["n_iter"] == 1
+    assert out["stats"]["n_mv"] == 13
+    pm = make_dipoles(p, 1).to("cuda:0").contiguous()
+    with pytest.raises(rid.RidError) as e:
+        prob.polarizability(pm, [5.0], "diag")
+    assert e.value.status == -8
+    ctx.close()

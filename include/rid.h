@@ -218,6 +218,26 @@ RID_API rid_status rid_response_solve(rid_problem* prob, const rid_solve_opts* o
                               double* alpha_host, double* u_dev, double* resid_host,
                               rid_stats* stats);
 
+/* ---- kernel profiling ---------------------------------------------------
+ * While enabled, every launch of the library's main kernel families on the
+ * context's stream is bracketed by HIP events.  rid_profile_read waits for
+ * the stream, returns per-family totals (launch count, summed event time,
+ * algorithmic FLOPs and bytes of the launches) and resets the counters.
+ * Families: "exch_s" (S^P = B_ij X), "exch_w" (sum_P S^P B_ab), "exch_q"
+ * (Q^P = B_ia X^T), "exch_wp" (sum_P Q^P B_ja), "coul_fwd", "coul_bwd",
+ * "combine", "ris_*" (the same families of the ris model), "gram", "combo",
+ * "small_dense". */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double flops;  /* algorithmic floating-point operations, summed */
+  double bytes;  /* algorithmic HBM bytes, summed */
+} rid_kernel_stat;
+
+RID_API rid_status rid_profile_enable(rid_context* ctx, int32_t on);
+RID_API rid_status rid_profile_read(rid_context* ctx, rid_kernel_stat* out, int32_t cap, int32_t* n);
+
 /* ---- batched solves (many molecules per launch) -------------------------
  * A request is an eigen-solve (kind 0: k, mode) or a polarizability solve
  * (kind 1: nrhs, p_dev, nfreq, omega_host).  Results are written into the

@@ -86,6 +86,11 @@ class rid_stats(ctypes.Structure):
                     bytes_resident=int(self.bytes_resident))
 
 
+class rid_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 class rid_request(ctypes.Structure):
     _fields_ = [
         ("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("mode", ctypes.c_int32),
@@ -131,6 +136,8 @@ PROTOTYPES = {
                               ctypes.POINTER(rid_stats)]),
     "rid_response_solve": (I32, [P, ctypes.POINTER(rid_solve_opts), I32, P, I32, DP, DP, P, DP,
                                  ctypes.POINTER(rid_stats)]),
+    "rid_profile_enable": (I32, [P, I32]),
+    "rid_profile_read": (I32, [P, ctypes.POINTER(rid_kernel_stat), I32, ctypes.POINTER(I32)]),
     "rid_batch_solve": (I32, [P, I32, PP, ctypes.POINTER(rid_request), ctypes.POINTER(rid_result)]),
     "rid_server_create": (I32, [P, ctypes.POINTER(rid_server_opts), PP]),
     "rid_server_submit": (I32, [P, P, ctypes.POINTER(rid_request), ctypes.POINTER(rid_result),
@@ -144,7 +151,7 @@ PROTOTYPES = {
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
-        raise ImportError("librid.so is not built (%s); run `python -m paper_2404_17133_amd.build` "
+        raise ImportError("librid.so is not built (%s); run `python paper_2404_17133_amd/build.py` "
                           "or __graft_entry__.build()" % path)
     lib = ctypes.CDLL(path)
     for name, (res, args) in PROTOTYPES.items():

@@ -1,6 +1,7 @@
 """Build librid.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2404_17133_amd.build [--jobs N]
+Usage: python paper_2404_17133_amd/build.py [--jobs N]
+(run as a script: importing the package would load the library being rebuilt)
 Objects go to paper_2404_17133_amd/_build/, the library to
 paper_2404_17133_amd/librid.so.
 """

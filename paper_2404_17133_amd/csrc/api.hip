@@ -287,6 +287,45 @@ rid_status rid_response_solve(rid_problem* prob, const rid_solve_opts* opts, int
   });
 }
 
+rid_status rid_profile_enable(rid_context* ctx, int32_t on) {
+  if (!ctx) return RID_ERR_INVALID_ARG;
+  return guarded(ctx, [&]() -> rid_status {
+    use_device(ctx);
+    RID_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->prof.resolve();
+    ctx->prof.on = on != 0;
+    return RID_OK;
+  });
+}
+
+rid_status rid_profile_read(rid_context* ctx, rid_kernel_stat* out, int32_t cap, int32_t* n) {
+  if (!ctx) return RID_ERR_INVALID_ARG;
+  return guarded(ctx, [&]() -> rid_status {
+    RID_CHECK(n && (out || cap == 0) && cap >= 0, RID_ERR_INVALID_ARG, "bad output arguments");
+    use_device(ctx);
+    RID_HIP(hipStreamSynchronize(ctx->stream));
+    rid::Profiler& p = ctx->prof;
+    p.resolve();
+    int cnt = 0;
+    for (size_t f = 0; f < p.names.size(); ++f) {
+      if (p.acc[f].launches == 0) continue;
+      if (cnt < cap) {
+        rid_kernel_stat& s = out[cnt];
+        std::memset(&s, 0, sizeof(s));
+        std::strncpy(s.name, p.names[f].c_str(), sizeof(s.name) - 1);
+        s.launches = p.acc[f].launches;
+        s.total_ms = p.acc[f].ms;
+        s.flops = p.acc[f].flops;
+        s.bytes = p.acc[f].bytes;
+      }
+      ++cnt;
+      p.acc[f] = rid::Profiler::Acc();
+    }
+    *n = cnt;
+    return RID_OK;
+  });
+}
+
 rid_status rid_batch_solve(rid_context* ctx, int32_t n, rid_problem* const* probs, const rid_request* reqs,
                            rid_result* results) {
   if (!ctx) return RID_ERR_INVALID_ARG;

@@ -22,6 +22,72 @@
 
 namespace rid {
 
+int Profiler::family(const char* name) {
+  auto it = ids.find(name);
+  if (it != ids.end()) return it->second;
+  const int id = (int)names.size();
+  names.push_back(name);
+  ids[name] = id;
+  acc.emplace_back();
+  return id;
+}
+
+hipEvent_t Profiler::get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  RID_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Profiler::resolve() {
+  for (const Rec& r : recs) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      Acc& a = acc[r.fam];
+      a.launches += 1;
+      a.ms += ms;
+      a.flops += r.flops;
+      a.bytes += r.bytes;
+    } else {
+      (void)hipGetLastError();
+    }
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+}
+
+Profiler::~Profiler() {
+  for (const Rec& r : recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(rid_context* c, const char* name, double fl, double by) : ctx(c), flops(fl), bytes(by) {
+  if (!ctx || !ctx->prof.on) return;
+  fam = ctx->prof.family(name);
+  a = ctx->prof.get_event();
+  RID_HIP(hipEventRecord(a, ctx->stream));
+}
+
+ProfScope::~ProfScope() {
+  if (fam < 0) return;
+  hipEvent_t b = nullptr;
+  try {
+    b = ctx->prof.get_event();
+  } catch (...) {
+    return;
+  }
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->prof.recs.push_back(Profiler::Rec{fam, a, b, flops, bytes});
+}
+
 void* dev_alloc(rid_context* ctx, size_t bytes) {
   if (bytes == 0) bytes = 256;
   void* p = nullptr;
@@ -101,6 +167,9 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
   typedef typename GemmTag<E>::type G;
   typedef typename AccOf<E>::type Acc;
   hipStream_t st = P->ctx->stream;
+  rid_context* ctx = P->ctx;
+  const std::string pre = ov.ris ? "ris_" : "";
+  const double esz = (double)sizeof(E), asz = (double)sizeof(Acc);
   OpWork& w = P->work;
   const int no = P->no, nv = P->nv;
   const long n = P->n();
@@ -144,11 +213,19 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
     g.sCs = (long)nvec * naux_j;
     g.alpha = 1.0;
     g.mode = GEMM_PARTIAL_SET;
-    gemm_nt<G>(g, 1, nsplit, st, 1);
+    {
+      ProfScope ps(ctx, (pre + "coul_fwd").c_str(), 2.0 * nvec * naux_j * (double)n,
+                   esz * ((double)naux_j * n + (double)nvec * n) + asz * nsplit * nvec * naux_j);
+      gemm_nt<G>(g, 1, nsplit, st, 1);
+    }
     reduce_splits<Acc>(w.tpart.as<Acc>(), nsplit, (long)nvec * naux_j, (long)nvec * naux_j, w.t64.as<double>(), st);
     t64 = w.t64.as<double>();
     w.jbuf.ensure(sizeof(double) * nvec * n);
-    coul_bwd<E>(t64, ov.b_ia, naux_j, n, nvec, w.jbuf.as<double>(), st);
+    {
+      ProfScope ps(ctx, (pre + "coul_bwd").c_str(), 2.0 * nvec * naux_j * (double)n,
+                   esz * (double)naux_j * n * ceil_div(nvec, 8) + 8.0 * nvec * n);
+      coul_bwd<E>(t64, ov.b_ia, naux_j, n, nvec, w.jbuf.as<double>(), st);
+    }
   }
 
   // 3. exchange products, chunked over the auxiliary index
@@ -196,6 +273,8 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
         g.sC1 = s_per_p;
         g.alpha = 1.0;
         g.mode = GEMM_STORE;
+        ProfScope ps(ctx, (pre + "exch_s").c_str(), 2.0 * no_a * (double)nvec * nv_a * no_a * pcc,
+                     esz * ((double)pcc * no_a * no_a + (double)nvec * nv_a * no_a + (double)pcc * s_per_p));
         gemm_nt<G>(g, pcc, 1, st);
       }
       {  // W += sum_P S^P B^P_ab (window)
@@ -217,6 +296,9 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
         g.sCs = part_elems;
         g.alpha = 1.0;
         g.mode = mode;
+        ProfScope ps(ctx, (pre + "exch_w").c_str(), 2.0 * rows * (double)nv_a * nv_a * pcc,
+                     esz * ((double)pcc * s_per_p + (double)pcc * nv_a * nv_a) +
+                         asz * part_elems * nsub * (mode == GEMM_PARTIAL_ADD ? 2.0 : 1.0));
         gemm_nt<G>(g, 1, nsub, st);
       }
       if (pair) {
@@ -238,6 +320,8 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
           g.sC1 = q_per_p;
           g.alpha = 1.0;
           g.mode = GEMM_STORE;
+          ProfScope ps(ctx, (pre + "exch_q").c_str(), 2.0 * no_a * (double)nvec * no_a * nv_a * pcc,
+                       esz * ((double)pcc * no_a * nv_a + (double)nvec * no_a * nv_a + (double)pcc * q_per_p));
           gemm_nt<G>(g, pcc, 1, st);
         }
         {  // W' += sum_P Q^P B^P_ja (window), B_ja read from the transposed copy
@@ -259,6 +343,9 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
           g.sCs = part_elems;
           g.alpha = 1.0;
           g.mode = mode;
+          ProfScope ps(ctx, (pre + "exch_wp").c_str(), 2.0 * rows * (double)nv_a * no_a * pcc,
+                       esz * ((double)pcc * q_per_p + (double)pcc * nv_a * no_a) +
+                           asz * part_elems * nsub * (mode == GEMM_PARTIAL_ADD ? 2.0 : 1.0));
           gemm_nt<G>(g, 1, nsub, st);
         }
       }
@@ -284,6 +371,8 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
   c.cj = pair ? 4.0 : 2.0;
   c.a_x = P->a_x;
   c.pair = pair ? 1 : 0;
+  ProfScope ps(ctx, (pre + "combine").c_str(), 0.0,
+               8.0 * nvec * n * (pair ? 5.0 : 3.0) + asz * (ns_w + ns_wp) * part_elems);
   combine<Acc>(c, exch ? w.wpart.as<Acc>() : nullptr, (exch && pair) ? w.wppart.as<Acc>() : nullptr, st);
 }
 
@@ -312,6 +401,7 @@ void apply_operator(rid_problem* P, int kind, int prec, int nvec, const double* 
     ov.i0 = i0;
     ov.no_a = no_a;
     ov.nv_a = nv_a;
+    ov.ris = ris;
     run_operator<double>(P, ov, pair, nvec, x, y, y2);
   } else if (prec == PREC_F32) {
     RID_CHECK(!ris, RID_ERR_DTYPE, "the ris operators run in FP64 or BF16");
@@ -326,6 +416,7 @@ void apply_operator(rid_problem* P, int kind, int prec, int nvec, const double* 
     ov.i0 = i0;
     ov.no_a = no_a;
     ov.nv_a = nv_a;
+    ov.ris = ris;
     run_operator<float>(P, ov, pair, nvec, x, y, y2);
   } else {
     P->ensure_bf16();
@@ -339,6 +430,7 @@ void apply_operator(rid_problem* P, int kind, int prec, int nvec, const double* 
     ov.i0 = i0;
     ov.no_a = no_a;
     ov.nv_a = nv_a;
+    ov.ris = ris;
     run_operator<uint16_t>(P, ov, pair, nvec, x, y, y2);
   }
 }

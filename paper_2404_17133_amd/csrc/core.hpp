@@ -2,11 +2,39 @@
 // operator driver.  Internal C++ (no exceptions cross the C ABI).
 #pragma once
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "common.hpp"
+
+namespace rid {
+
+// Event-bracketed launch timing per kernel family (enabled on demand).
+struct Profiler {
+  struct Rec {
+    int fam;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  struct Acc {
+    int64_t launches = 0;
+    double ms = 0.0, flops = 0.0, bytes = 0.0;
+  };
+  bool on = false;
+  std::vector<std::string> names;
+  std::map<std::string, int> ids;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  std::vector<Acc> acc;
+  int family(const char* name);
+  hipEvent_t get_event();
+  void resolve();  // stream must be idle
+  ~Profiler();
+};
+
+}  // namespace rid
 
 struct rid_context {
   int device = 0;
@@ -15,7 +43,22 @@ struct rid_context {
   bool user_alloc = false;
   std::string last_error;
   std::mutex mu;  // guards allocator use from the server thread
+  rid::Profiler prof;
 };
+
+namespace rid {
+
+// RAII bracket of one launch (no-op unless profiling is enabled).
+struct ProfScope {
+  rid_context* ctx;
+  int fam = -1;
+  hipEvent_t a = nullptr;
+  double flops, bytes;
+  ProfScope(rid_context* c, const char* name, double fl, double by);
+  ~ProfScope();
+};
+
+}  // namespace rid
 
 namespace rid {
 
@@ -60,6 +103,7 @@ struct OpView {
   int naux_j = 0;           // rows in the Coulomb part
   int naux_k = 0;           // leading rows in the exchange part
   int i0 = 0, no_a = 0, nv_a = 0;  // exchange window
+  bool ris = false;                 // profiling family prefix
 };
 
 }  // namespace rid

@@ -9,8 +9,11 @@
 // others rotated), computes the m/2 annihilating rotations from the current
 // matrix, applies them to the rows, then to the columns and to the
 // eigenvector matrix; disjoint rotations commute, so each phase is fully
-// parallel.  Sweeps stop when the squared off-diagonal Frobenius norm falls
-// below 1e-30 of the squared full norm.
+// parallel.  A pair is rotated only while |a_pq| exceeds both
+// 1e-15 sqrt(|a_pp a_qq|) (the classical threshold rule) and 4e-16 ||a||_F
+// (the rounding level of the entries, so that rounding residue never
+// re-triggers rotations); the sweeps stop after a sweep in which no pair
+// needed a rotation (at most 40 sweeps).
 #include <algorithm>
 
 #include "engkern.hpp"
@@ -35,29 +38,26 @@ __device__ double block_sum(double v, double* red) {
 
 // work: m*m + m doubles
 __global__ __launch_bounds__(DB) void jacobi_kernel(double* a, int m, int lda, double* w, double* q, double* work) {
-  __shared__ double red[16];
   __shared__ double cs[MAXM / 2], sn[MAXM / 2];
   __shared__ int pp[MAXM / 2], qq[MAXM / 2];
   __shared__ int rank[MAXM];
-  __shared__ int stop;
+  __shared__ int nrot;
+  __shared__ double red[16];
   const int tid = threadIdx.x;
-  for (int t = tid; t < m * m; t += DB) q[t] = (t / m == t % m) ? 1.0 : 0.0;
+  double fro = 0.0;
+  for (int t = tid; t < m * m; t += DB) {
+    q[t] = (t / m == t % m) ? 1.0 : 0.0;
+    const double v = a[(long)(t / m) * lda + t % m];
+    fro += v * v;
+  }
+  fro = sqrt(block_sum(fro, red));
+  const double floor_abs = 4e-16 * fro;  // rounding level of the matrix entries
   const int mm = m + (m & 1);
   const int npair = mm / 2;
   __syncthreads();
-  for (int sweep = 0; sweep < 60 && m > 1; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int t = tid; t < m * m; t += DB) {
-      const int i = t / m, j = t % m;
-      const double v = a[(long)i * lda + j];
-      tot += v * v;
-      if (i != j) off += v * v;
-    }
-    off = block_sum(off, red);
-    tot = block_sum(tot, red);
-    if (tid == 0) stop = (off <= 1e-30 * tot) || tot == 0.0;
+  for (int sweep = 0; sweep < 40 && m > 1; ++sweep) {
+    if (tid == 0) nrot = 0;
     __syncthreads();
-    if (stop) break;
     for (int r = 0; r < mm - 1; ++r) {
       if (tid < npair) {
         // round-robin slots: slot 0 fixed, slots 1..mm-1 shifted by r
@@ -72,12 +72,15 @@ __global__ __launch_bounds__(DB) void jacobi_kernel(double* a, int m, int lda, d
         double c = 1.0, s = 0.0;
         if (qv < m) {
           const double apq = a[(long)p * lda + qv];
-          if (apq != 0.0) {
-            const double app = a[(long)p * lda + p], aqq = a[(long)qv * lda + qv];
+          const double app = a[(long)p * lda + p], aqq = a[(long)qv * lda + qv];
+          // rotate only while the coupling is above rounding level relative
+          // to the two diagonal entries (the classical cyclic-Jacobi rule)
+          if (fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq)) && fabs(apq) > floor_abs) {
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
+            atomicAdd(&nrot, 1);
           }
         }
         pp[tid] = p;
@@ -113,6 +116,9 @@ __global__ __launch_bounds__(DB) void jacobi_kernel(double* a, int m, int lda, d
       }
       __syncthreads();
     }
+    const bool done = nrot == 0;
+    __syncthreads();  // every thread has read nrot before it is reset
+    if (done) break;
   }
   // ascending order, ties by index
   double* wd = work + (long)m * m;
@@ -135,6 +141,268 @@ __global__ __launch_bounds__(DB) void jacobi_kernel(double* a, int m, int lda, d
   for (int j = tid; j < m; j += DB) w[rank[j]] = wd[j];
   __syncthreads();
   for (int t = tid; t < m * m; t += DB) q[t] = work[t];
+}
+
+// k lowest eigenpairs of a symmetric matrix: Householder reduction to
+// tridiagonal form T = H^T a H (H = H_0 ... H_{m-3}), Sturm-count bisection
+// for the eigenvalues of T, inverse iteration with partial pivoting for its
+// eigenvectors (re-orthogonalised within clusters of close eigenvalues at
+// every iteration), and back-transformation by the reflectors.
+// work: 3 m + 6 m k + 2 m doubles.
+__device__ inline int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int m, double x,
+                                  double pivmin) {
+  int cnt = 0;
+  double qv = d[0] - x;
+  if (fabs(qv) < pivmin) qv = -pivmin;
+  cnt += qv < 0.0;
+  for (int i = 1; i < m; ++i) {
+    qv = d[i] - x - e2[i - 1] / qv;
+    if (fabs(qv) < pivmin) qv = -pivmin;
+    cnt += qv < 0.0;
+  }
+  return cnt;
+}
+
+__global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, int k, double* w, double* q, int ldq,
+                                                   double* work) {
+  __shared__ double v[MAXM];
+  __shared__ double wv[MAXM];
+  __shared__ double part[DB];
+  __shared__ double red[16];
+  __shared__ double sc[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* d = work;
+  double* e = work + m;
+  double* e2 = work + 2 * m;
+  double* y = work + 3 * m;              // k vectors of length m
+  double* fu = y + (long)k * m;          // factor storage per vector: u, s1, s2, l, piv
+  double* fs1 = fu + (long)k * m;
+  double* fs2 = fs1 + (long)k * m;
+  double* fl = fs2 + (long)k * m;
+  double* fp = fl + (long)k * m;
+  int* refl = reinterpret_cast<int*>(fp + (long)k * m);  // reflector present flags (m ints)
+
+  // ---- 1. tridiagonalisation ------------------------------------------------
+  for (int j = 0; j + 2 < m; ++j) {
+    const int n1 = m - j - 1;
+    double ss = 0.0;
+    for (int r = tid; r < n1; r += DB) {
+      const double x = a[(long)(j + 1 + r) * lda + j];
+      v[r] = x;
+      ss += x * x;
+    }
+    ss = block_sum(ss, red);  // includes a barrier after the writes to v
+    const double x0 = v[0];
+    const double tail = ss - x0 * x0;
+    if (tid == 0) d[j] = a[(long)j * lda + j];
+    if (tail <= 1e-300 * (1.0 + ss)) {
+      // column already reduced: no reflector
+      if (tid == 0) {
+        e[j] = x0;
+        refl[j] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+    const double sigma = sqrt(ss);
+    const double alpha = x0 >= 0.0 ? -sigma : sigma;
+    const double vn = sqrt(tail + (x0 - alpha) * (x0 - alpha));
+    __syncthreads();
+    for (int r = tid; r < n1; r += DB) {
+      const double vr = (r == 0 ? x0 - alpha : v[r]) / vn;
+      v[r] = vr;
+      a[(long)(j + 1 + r) * lda + j] = vr;  // keep the reflector for the back-transformation
+    }
+    if (tid == 0) {
+      e[j] = alpha;
+      refl[j] = 1;
+    }
+    __syncthreads();
+    // p = A_t v, A_t the trailing block (symmetric): column sums, rows split in R groups
+    const int cw = ((n1 + 63) / 64) * 64;
+    const int rg = max(1, DB / cw);
+    {
+      const int c = tid % cw, g = tid / cw;
+      if (g < rg) {
+        double acc = 0.0;
+        if (c < n1)
+          for (int r = g; r < n1; r += rg) acc += a[(long)(j + 1 + r) * lda + (j + 1 + c)] * v[r];
+        part[g * cw + c] = acc;
+      }
+    }
+    __syncthreads();
+    double kp = 0.0;
+    for (int c = tid; c < n1; c += DB) {
+      double pc = 0.0;
+      for (int g = 0; g < rg; ++g) pc += part[g * cw + c];
+      wv[c] = pc;
+      kp += pc * v[c];
+    }
+    kp = block_sum(kp, red);  // barrier: wv complete
+    for (int c = tid; c < n1; c += DB) wv[c] -= kp * v[c];
+    __syncthreads();
+    // A_t -= 2 (v w^T + w v^T)
+    for (long idx = tid; idx < (long)n1 * n1; idx += DB) {
+      const int r = (int)(idx / n1), c = (int)(idx - (long)r * n1);
+      a[(long)(j + 1 + r) * lda + (j + 1 + c)] -= 2.0 * (v[r] * wv[c] + wv[r] * v[c]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (m >= 2) {
+      d[m - 2] = a[(long)(m - 2) * lda + (m - 2)];
+      e[m - 2] = a[(long)(m - 1) * lda + (m - 2)];
+      if (m - 2 >= 0) refl[m - 2] = 0;
+    }
+    d[m - 1] = a[(long)(m - 1) * lda + (m - 1)];
+    e[m - 1] = 0.0;
+    refl[m - 1] = 0;
+  }
+  __syncthreads();
+  // ---- 2. bisection -----------------------------------------------------------
+  double tn = 0.0;
+  for (int i = tid; i < m; i += DB) {
+    e2[i] = e[i] * e[i];
+    tn = fmax(tn, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
+  }
+  // max reduction through the sum helper on squared-free values: use a wave max
+  for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
+  __syncthreads();
+  if (lane == 0) red[wave] = tn;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < DB / 64; ++i) t = fmax(t, red[i]);
+    sc[0] = t;
+  }
+  __syncthreads();
+  const double tnorm = fmax(sc[0], 1e-300);
+  const double pivmin = 1e-300 + 1e-30 * tnorm * tnorm;
+  if (tid < k) {
+    double lo = -tnorm, hi = tnorm;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (hi - lo <= 2.2e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
+      if (sturm_count(d, e2, m, mid, pivmin) > tid)
+        hi = mid;
+      else
+        lo = mid;
+    }
+    w[tid] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // ---- 3. inverse iteration ---------------------------------------------------
+  // factor T - lambda_t I with partial pivoting (thread t), rows i, i+1 swapped
+  // when |e_i| > |u_i|; u diagonal, s1/s2 the two superdiagonals, l multipliers.
+  if (tid < k) {
+    const double lam = w[tid];
+    double* u = fu + (long)tid * m;
+    double* s1 = fs1 + (long)tid * m;
+    double* s2 = fs2 + (long)tid * m;
+    double* l = fl + (long)tid * m;
+    double* pv = fp + (long)tid * m;
+    const double eps_piv = 2.2e-16 * tnorm;
+    double di = d[0] - lam, ci = m > 1 ? e[0] : 0.0;  // current row: diag, super
+    for (int i = 0; i < m - 1; ++i) {
+      const double bi = e[i];                // subdiagonal below the current row
+      const double dn = d[i + 1] - lam;       // next row diag
+      const double cn = (i + 1 < m - 1) ? e[i + 1] : 0.0;  // next row super
+      if (fabs(di) >= fabs(bi)) {
+        // no swap: eliminate next row with the current one
+        const double piv = fabs(di) < eps_piv ? (di < 0 ? -eps_piv : eps_piv) : di;
+        const double mult = bi / piv;
+        u[i] = piv;
+        s1[i] = ci;
+        s2[i] = 0.0;
+        l[i] = mult;
+        pv[i] = 0.0;
+        di = dn - mult * ci;
+        ci = cn;
+      } else {
+        // swap rows i and i+1
+        const double mult = di / bi;
+        u[i] = bi;
+        s1[i] = dn;
+        s2[i] = cn;
+        l[i] = mult;
+        pv[i] = 1.0;
+        di = ci - mult * dn;
+        ci = -mult * cn;
+      }
+    }
+    u[m - 1] = fabs(di) < eps_piv ? (di < 0 ? -eps_piv : eps_piv) : di;
+    // starting vector: deterministic, not orthogonal to any eigenvector in practice
+    double* yt = y + (long)tid * m;
+    for (int i = 0; i < m; ++i) yt[i] = 1.0 + 0.01 * (double)((i * 7919 + tid * 104729) % 101) / 101.0;
+  }
+  __syncthreads();
+  for (int iter = 0; iter < 4; ++iter) {
+    if (tid < k) {
+      const double* u = fu + (long)tid * m;
+      const double* s1 = fs1 + (long)tid * m;
+      const double* s2 = fs2 + (long)tid * m;
+      const double* l = fl + (long)tid * m;
+      const double* pv = fp + (long)tid * m;
+      double* yt = y + (long)tid * m;
+      // forward: apply the row interchanges and multipliers
+      for (int i = 0; i < m - 1; ++i) {
+        if (pv[i] != 0.0) {
+          const double t = yt[i];
+          yt[i] = yt[i + 1];
+          yt[i + 1] = t - l[i] * yt[i];
+        } else {
+          yt[i + 1] -= l[i] * yt[i];
+        }
+      }
+      // backward: upper triangular with two superdiagonals
+      for (int i = m - 1; i >= 0; --i) {
+        double t = yt[i];
+        if (i + 1 < m) t -= s1[i] * yt[i + 1];
+        if (i + 2 < m) t -= s2[i] * yt[i + 2];
+        yt[i] = t / u[i];
+      }
+    }
+    __syncthreads();
+    // normalise and re-orthogonalise within clusters, in ascending order
+    for (int t = 0; t < k; ++t) {
+      double* yt = y + (long)t * m;
+      const double lt = w[t];
+      int t0 = t;
+      while (t0 > 0 && fabs(w[t0 - 1] - w[t0]) <= 1e-3 * tnorm) --t0;
+      for (int s = t0; s < t; ++s) {
+        const double* ys = y + (long)s * m;
+        double dp = 0.0;
+        for (int i = tid; i < m; i += DB) dp += ys[i] * yt[i];
+        dp = block_sum(dp, red);
+        for (int i = tid; i < m; i += DB) yt[i] -= dp * ys[i];
+        __syncthreads();
+      }
+      double nn = 0.0;
+      for (int i = tid; i < m; i += DB) nn += yt[i] * yt[i];
+      nn = block_sum(nn, red);
+      const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+      for (int i = tid; i < m; i += DB) yt[i] *= inv;
+      __syncthreads();
+      (void)lt;
+    }
+  }
+  // ---- 4. back-transformation, one wave per vector ----------------------------
+  for (int t = wave; t < k; t += DB / 64) {
+    double* yt = y + (long)t * m;
+    for (int j = m - 3; j >= 0; --j) {
+      if (!refl[j]) continue;
+      const int n1 = m - j - 1;
+      double dp = 0.0;
+      for (int r = lane; r < n1; r += 64) dp += a[(long)(j + 1 + r) * lda + j] * yt[j + 1 + r];
+      dp = wave_sum(dp);
+      for (int r = lane; r < n1; r += 64) yt[j + 1 + r] -= 2.0 * dp * a[(long)(j + 1 + r) * lda + j];
+    }
+  }
+  __syncthreads();
+  for (long idx = tid; idx < (long)m * k; idx += DB) {
+    const int i = (int)(idx / k), t = (int)(idx - (long)i * k);
+    q[(long)i * ldq + t] = y[(long)t * m + i];
+  }
 }
 
 // Cholesky, left-looking by columns.
@@ -294,6 +562,40 @@ __global__ void small_gemm_kernel(int ta, int tb, int m, int n, int k, double al
   }
 }
 
+// G = L^{-1} for lower-triangular L, one column per thread.
+__global__ void trinv_lower_kernel(const double* __restrict__ L, int m, int ldl, double* __restrict__ G, int ldg) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  for (int i = 0; i < c; ++i) G[(long)i * ldg + c] = 0.0;
+  G[(long)c * ldg + c] = 1.0 / L[(long)c * ldl + c];
+  for (int i = c + 1; i < m; ++i) {
+    double acc = 0.0;
+    for (int k = c; k < i; ++k) acc += L[(long)i * ldl + k] * G[(long)k * ldg + c];
+    G[(long)i * ldg + c] = -acc / L[(long)i * ldl + i];
+  }
+}
+
+// mats_b = t - sh_b^2 w  (m x m each)
+__global__ void build_schur_kernel(const double* __restrict__ t, int ldt, const double* __restrict__ w, int ldw, int m,
+                                   const double* __restrict__ sh, double* __restrict__ mats) {
+  const int b = blockIdx.y;
+  const double s2 = sh[b] * sh[b];
+  double* out = mats + (long)b * m * m;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m * m; e += gridDim.x * blockDim.x) {
+    const int i = e / m, j = e - i * m;
+    out[e] = t[(long)i * ldt + j] - s2 * w[(long)i * ldw + j];
+  }
+}
+
+// out_b = x_b + sh_b * y_b for rows b < nb of length m
+__global__ void rows_axpy_kernel(const double* __restrict__ x, int ldx, const double* __restrict__ y, int ldy,
+                                 const double* __restrict__ sh, int nb, int m, double* __restrict__ out, int ldo) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb * m) return;
+  const int b = t / m, i = t - b * m;
+  out[(long)b * ldo + i] = x[(long)b * ldx + i] + sh[b] * y[(long)b * ldy + i];
+}
+
 __global__ void symmetrize_kernel(double* a, int m, int lda) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m * m) return;
@@ -345,6 +647,16 @@ void small_eigh(double* a, int m, int lda, double* w, double* q, double* work, h
   RID_HIP(hipGetLastError());
 }
 
+size_t small_syevx_work(int m, int k) { return (size_t)3 * m + (size_t)6 * m * k + 2 * (size_t)m + 64; }
+
+void small_syevx(double* a, int m, int lda, int k, double* w, double* q, int ldq, double* work, hipStream_t s) {
+  if (m <= 0 || k <= 0) return;
+  RID_CHECK(m <= MAXM, RID_ERR_SHAPE, "projected dimension above 1024");
+  RID_CHECK(k <= m && k <= DB, RID_ERR_SHAPE, "k must be <= m and <= 1024");
+  hipLaunchKernelGGL(syevx_kernel, dim3(1), dim3(DB), 0, s, a, m, lda, k, w, q, ldq, work);
+  RID_HIP(hipGetLastError());
+}
+
 void small_chol(double* a, int m, int lda, int* info, hipStream_t s) {
   if (m <= 0) return;
   hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(DB), 0, s, a, m, lda, info);
@@ -362,6 +674,28 @@ void small_gemm(int ta, int tb, int m, int n, int k, double alpha, const double*
   if (m <= 0 || n <= 0) return;
   dim3 grid((unsigned)ceil_div(n, 16), (unsigned)ceil_div(m, 16));
   hipLaunchKernelGGL(small_gemm_kernel, grid, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  RID_HIP(hipGetLastError());
+}
+
+void small_trinv_lower(const double* L, int m, int ldl, double* G, int ldg, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(trinv_lower_kernel, dim3(ceil_div(m, 64)), dim3(64), 0, s, L, m, ldl, G, ldg);
+  RID_HIP(hipGetLastError());
+}
+
+void build_schur(const double* t, int ldt, const double* w, int ldw, int m, const double* sh, int nb, double* mats,
+                 hipStream_t s) {
+  if (m <= 0 || nb <= 0) return;
+  dim3 grid((unsigned)std::min(ceil_div(m * m, 256), 1024), (unsigned)nb);
+  hipLaunchKernelGGL(build_schur_kernel, grid, dim3(256), 0, s, t, ldt, w, ldw, m, sh, mats);
+  RID_HIP(hipGetLastError());
+}
+
+void rows_axpy(const double* x, int ldx, const double* y, int ldy, const double* sh, int nb, int m, double* out,
+               int ldo, hipStream_t s) {
+  if (m <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL(rows_axpy_kernel, dim3(ceil_div(nb * m, 256)), dim3(256), 0, s, x, ldx, y, ldy, sh, nb, m, out,
+                     ldo);
   RID_HIP(hipGetLastError());
 }
 

@@ -111,6 +111,7 @@ struct Basis {
 // basis and each other, append the accepted ones.  Returns the number added.
 int append_orthonormal(Eng& E, Basis& B, double* W, int nnew, double drop_tol = 1e-8) {
   if (nnew <= 0) return 0;
+  ProfScope ps(E.P->ctx, "orthonormalize", 0.0, 0.0);
   const long N = E.N;
   RID_CHECK(B.m + nnew <= B.cap, RID_ERR_INTERNAL, "basis capacity exceeded");
   E.tmp1.ensure(sizeof(double) * (size_t)std::max(B.m, 1) * nnew + 64 * sizeof(double));
@@ -173,6 +174,7 @@ void project(Eng& E, Basis& B, int m0) {
   const int m = B.m, nn = m - m0;
   if (nn <= 0) return;
   const long N = E.N;
+  ProfScope ps(E.P->ctx, "project", 4.0 * m * nn * (double)N * B.nprod, 8.0 * 2 * (m + nn) * (double)N * B.nprod);
   DevBuf c1(E.P->ctx), c2(E.P->ctx);
   c1.ensure(sizeof(double) * (size_t)m * nn);
   c2.ensure(sizeof(double) * (size_t)m * nn);
@@ -206,18 +208,23 @@ int default_m_max(int k, int m_max) { return m_max > 0 ? m_max : std::max(200, 4
 // ---------------------------------------------------------------------------
 struct Ritz {
   DevBuf acopy, w, q, work, lmat, t1, mmat, zc, zpc, om, info;
+  int ldq = 0;  // leading dimension of q (the number of eigenpairs computed)
   Ritz(rid_context* c) : acopy(c), w(c), q(c), work(c), lmat(c), t1(c), mmat(c), zc(c), zpc(c), om(c), info(c) {}
 };
 
-// TDA: eigenpairs of a (m x m) -> w (device, m), q (device, m x m).
-void ritz_sym(Eng& E, Ritz& R, Basis& B) {
+// TDA: the nq lowest eigenpairs of a (m x m) -> w (device, nq), q (device,
+// m x nq, ld R.ldq = nq).
+void ritz_sym(Eng& E, Ritz& R, Basis& B, int nq) {
   const int m = B.m;
+  nq = std::max(1, std::min(nq, m));
   R.acopy.ensure(sizeof(double) * (size_t)m * m);
-  R.w.ensure(sizeof(double) * m);
-  R.q.ensure(sizeof(double) * (size_t)m * m);
-  R.work.ensure(sizeof(double) * ((size_t)m * m + m));
+  R.w.ensure(sizeof(double) * nq);
+  R.q.ensure(sizeof(double) * (size_t)m * nq);
+  R.work.ensure(sizeof(double) * small_syevx_work(m, nq));
+  R.ldq = nq;
+  ProfScope ps(E.P->ctx, "small_dense", 0.0, 0.0);
   copy_block(B.a1.as<double>(), B.cap, m, m, R.acopy.as<double>(), m, E.st);
-  small_eigh(R.acopy.as<double>(), m, m, R.w.as<double>(), R.q.as<double>(), R.work.as<double>(), E.st);
+  small_syevx(R.acopy.as<double>(), m, m, nq, R.w.as<double>(), R.q.as<double>(), nq, R.work.as<double>(), E.st);
 }
 
 __global__ void rpa_scale_kernel(const double* __restrict__ w2, int k, double* __restrict__ om,
@@ -247,32 +254,36 @@ void ritz_rpa(Eng& E, Ritz& R, Basis& B, int k, std::vector<double>& w2_host, in
   R.lmat.ensure(sizeof(double) * (size_t)m * m);
   R.t1.ensure(sizeof(double) * (size_t)m * m);
   R.mmat.ensure(sizeof(double) * (size_t)m * m);
-  R.w.ensure(sizeof(double) * m);
-  R.q.ensure(sizeof(double) * (size_t)m * m);
-  R.work.ensure(sizeof(double) * ((size_t)m * m + m));
+  R.w.ensure(sizeof(double) * kk);
+  R.q.ensure(sizeof(double) * (size_t)m * kk);
+  R.work.ensure(sizeof(double) * small_syevx_work(m, kk));
+  R.ldq = kk;
   R.zc.ensure(sizeof(double) * (size_t)m * kk);
   R.zpc.ensure(sizeof(double) * (size_t)m * kk);
   R.om.ensure(sizeof(double) * 3 * kk);
   R.info.ensure(sizeof(int) * 4);
+  {
+  ProfScope ps(E.P->ctx, "small_dense", 0.0, 0.0);
   copy_block(B.a2.as<double>(), B.cap, m, m, R.lmat.as<double>(), m, E.st);
   small_chol(R.lmat.as<double>(), m, m, R.info.as<int>(), E.st);
   // M = L^T a_+ L
   small_gemm(0, 0, m, m, m, 1.0, B.a1.as<double>(), B.cap, R.lmat.as<double>(), m, 0.0, R.t1.as<double>(), m, E.st);
   small_gemm(1, 0, m, m, m, 1.0, R.lmat.as<double>(), m, R.t1.as<double>(), m, 0.0, R.mmat.as<double>(), m, E.st);
   small_symmetrize(R.mmat.as<double>(), m, m, E.st);
-  small_eigh(R.mmat.as<double>(), m, m, R.w.as<double>(), R.q.as<double>(), R.work.as<double>(), E.st);
+  small_syevx(R.mmat.as<double>(), m, m, kk, R.w.as<double>(), R.q.as<double>(), kk, R.work.as<double>(), E.st);
   double* om = R.om.as<double>();
   double* f1 = om + kk;
   double* f2 = om + 2 * kk;
   hipLaunchKernelGGL(rpa_scale_kernel, dim3(1), dim3(256), 0, E.st, R.w.as<double>(), kk, om, f1, f2);
   // z = L q[:, :k] / sqrt(Omega), z' = a_+ z / Omega
-  small_gemm(0, 0, m, kk, m, 1.0, R.lmat.as<double>(), m, R.q.as<double>(), m, 0.0, R.zc.as<double>(), kk, E.st);
+  small_gemm(0, 0, m, kk, m, 1.0, R.lmat.as<double>(), m, R.q.as<double>(), kk, 0.0, R.zc.as<double>(), kk, E.st);
   hipLaunchKernelGGL(scale_small_cols_kernel, dim3(ceil_div(m * kk, 256)), dim3(256), 0, E.st, R.zc.as<double>(), m,
                      kk, kk, f1);
   small_gemm(0, 0, m, kk, m, 1.0, B.a1.as<double>(), B.cap, R.zc.as<double>(), kk, 0.0, R.zpc.as<double>(), kk, E.st);
   hipLaunchKernelGGL(scale_small_cols_kernel, dim3(ceil_div(m * kk, 256)), dim3(256), 0, E.st, R.zpc.as<double>(), m,
                      kk, kk, f2);
   RID_HIP(hipGetLastError());
+  }
   w2_host.resize(kk);
   E.d2h(w2_host.data(), R.w.as<double>(), sizeof(double) * kk);
   int info = 0;
@@ -338,8 +349,11 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
       RedScratch rs = E.rs(nr, m);
       gram(rh.as<double>(), N, nr, U.V(0), N, m, N, gbuf.as<double>(), m, rs, E.st);  // g[n][i]
     }
-    build_shifted(U.a1.as<double>(), nullptr, m, U.cap, sh, nr, 0, mats.as<double>(), E.st);
-    small_lu_solve(mats.as<double>(), gbuf.as<double>(), m, nr, E.st);  // y[n][i]
+    {
+      ProfScope ps(E.P->ctx, "inner_solve", 0.0, 0.0);
+      build_shifted(U.a1.as<double>(), nullptr, m, U.cap, sh, nr, 0, mats.as<double>(), E.st);
+      small_lu_solve(mats.as<double>(), gbuf.as<double>(), m, nr, E.st);  // y[n][i]
+    }
     combo(U.V(0), N, m, gbuf.as<double>(), 1, m, nr, N, 1.0, 0.0, sol.as<double>(), N, E.st);
     combo(U.P1(0), N, m, gbuf.as<double>(), 1, m, nr, N, 1.0, 0.0, tuy.as<double>(), N, E.st);
     resid3(tuy.as<double>(), sol.as<double>(), rh.as<double>(), N, nr, N, sh, rho.as<double>(), N, E.st);
@@ -376,6 +390,47 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
   return res;
 }
 
+// Projected pair systems [[t+, -s_b I], [-s_b I, t-]] (y_b; y'_b) = (g1_b; g2_b)
+// for b < nb; g (rows of length 2m: g1 then g2) is overwritten by (y; y').
+// With t- = L L^T positive definite the second block is eliminated:
+//   (t+ - s^2 W) y = g1 + s W g2,  y' = W (g2 + s y),  W = t-^{-1} = G^T G, G = L^{-1},
+// so every right-hand side needs one m x m solve (one Cholesky and one
+// triangular inverse shared by all of them).  If t- is not positive definite
+// the full 2m x 2m systems are solved instead.
+void solve_pair_systems(Eng& E, Basis& U, int m, const double* sh, int nb, double* g, DevBuf& mats, DevBuf& work) {
+  const int d = 2 * m;
+  ProfScope ps(E.P->ctx, "inner_solve", 0.0, 0.0);
+  work.ensure(sizeof(double) * ((size_t)3 * m * m + (size_t)2 * nb * m + 8));
+  double* L = work.as<double>();
+  double* G = L + (size_t)m * m;
+  double* W = G + (size_t)m * m;
+  double* tmp = W + (size_t)m * m;  // nb x m
+  double* rhs = tmp + (size_t)nb * m;  // nb x m
+  int* info = reinterpret_cast<int*>(rhs + (size_t)nb * m);
+  copy_block(U.a2.as<double>(), U.cap, m, m, L, m, E.st);
+  small_chol(L, m, m, info, E.st);
+  int inf = 0;
+  E.d2h(&inf, info, sizeof(int));
+  if (inf != 0) {
+    mats.ensure(sizeof(double) * (size_t)nb * d * d);
+    build_shifted(U.a1.as<double>(), U.a2.as<double>(), m, U.cap, sh, nb, 1, mats.as<double>(), E.st);
+    small_lu_solve(mats.as<double>(), g, d, nb, E.st);
+    return;
+  }
+  small_trinv_lower(L, m, m, G, m, E.st);
+  small_gemm(1, 0, m, m, m, 1.0, G, m, G, m, 0.0, W, m, E.st);
+  // tmp = g2 W ; rhs = g1 + s tmp
+  small_gemm(0, 0, nb, m, m, 1.0, g + m, d, W, m, 0.0, tmp, m, E.st);
+  rows_axpy(g, d, tmp, m, sh, nb, m, rhs, m, E.st);
+  mats.ensure(sizeof(double) * (size_t)nb * m * m);
+  build_schur(U.a1.as<double>(), U.cap, W, m, m, sh, nb, mats.as<double>(), E.st);
+  small_lu_solve(mats.as<double>(), rhs, m, nb, E.st);  // rhs <- y
+  // y' = (g2 + s y) W
+  rows_axpy(g + m, d, rhs, m, sh, nb, m, tmp, m, E.st);
+  small_gemm(0, 0, nb, m, m, 1.0, tmp, m, W, m, 0.0, g + m, d, E.st);
+  copy_block(rhs, m, nb, m, g, d, E.st);
+}
+
 // Solve [[T+, -s_n], [-s_n, T-]] (d1; d2) = (r1; r2) approximately.
 InnerResult inner_pair(Eng& E, int prec, const double* r1, const double* r2, int nr, const std::vector<double>& sh_host,
                        double tol, int max_iter, double* out1, double* out2) {
@@ -384,7 +439,7 @@ InnerResult inner_pair(Eng& E, int prec, const double* r1, const double* r2, int
   rid_context* ctx = E.P->ctx;
   const long N = E.N;
   DevBuf h1(ctx), h2(ctx), nrm(ctx), n1(ctx), shd(ctx), idxd(ctx), wn(ctx), gbuf(ctx), mats(ctx), s1(ctx), s2(ctx),
-      ty(ctx), rho1(ctx), rho2(ctx), rnd(ctx);
+      ty(ctx), rho1(ctx), rho2(ctx), rnd(ctx), schur(ctx);
   h1.ensure(sizeof(double) * nr * N);
   h2.ensure(sizeof(double) * nr * N);
   nrm.ensure(sizeof(double) * nr);
@@ -433,14 +488,12 @@ InnerResult inner_pair(Eng& E, int prec, const double* r1, const double* r2, int
     const int m = U.m;
     const int d = 2 * m;
     gbuf.ensure(sizeof(double) * (size_t)nr * d);
-    mats.ensure(sizeof(double) * (size_t)nr * d * d);
     {
       RedScratch rs = E.rs(nr, m);
       gram(h1.as<double>(), N, nr, U.V(0), N, m, N, gbuf.as<double>(), d, rs, E.st);
       gram(h2.as<double>(), N, nr, U.V(0), N, m, N, gbuf.as<double>() + m, d, rs, E.st);
     }
-    build_shifted(U.a1.as<double>(), U.a2.as<double>(), m, U.cap, sh, nr, 1, mats.as<double>(), E.st);
-    small_lu_solve(mats.as<double>(), gbuf.as<double>(), d, nr, E.st);
+    solve_pair_systems(E, U, m, sh, nr, gbuf.as<double>(), mats, schur);
     const double* y1 = gbuf.as<double>();
     const double* y2 = gbuf.as<double>() + m;
     combo(U.V(0), N, m, y1, 1, d, nr, N, 1.0, 0.0, s1.as<double>(), N, E.st);
@@ -534,10 +587,10 @@ void davidson_sym(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
     const int m = B.m;
     const int kk = std::min(kk0, m);
     auto t0 = Clock::now();
-    ritz_sym(E, R, B);
+    ritz_sym(E, R, B, std::max(kk, keep));
     // X = V q[:, :k], AX = AV q[:, :k], R = AX - w X
-    combo(B.V(0), N, m, R.q.as<double>(), m, 1, kk, N, 1.0, 0.0, xout, N, E.st);
-    combo(B.P1(0), N, m, R.q.as<double>(), m, 1, kk, N, 1.0, 0.0, ax.as<double>(), N, E.st);
+    combo(B.V(0), N, m, R.q.as<double>(), R.ldq, 1, kk, N, 1.0, 0.0, xout, N, E.st);
+    combo(B.P1(0), N, m, R.q.as<double>(), R.ldq, 1, kk, N, 1.0, 0.0, ax.as<double>(), N, E.st);
     residual(ax.as<double>(), xout, N, kk, N, R.w.as<double>(), r.as<double>(), E.st);
     {
       RedScratch rs = E.rs(1, kk);
@@ -569,11 +622,11 @@ void davidson_sym(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
     if (B.m + nnew > m_max) {
       // restart on the leading Ritz vectors: exact by linearity, and the
       // projected matrix of the collapsed basis is diag(w)
-      const int kp = std::min(keep, m);
+      const int kp = std::min(keep, R.ldq);
       vtmp.ensure(sizeof(double) * kp * N);
       ptmp.ensure(sizeof(double) * kp * N);
-      combo(B.V(0), N, m, R.q.as<double>(), m, 1, kp, N, 1.0, 0.0, vtmp.as<double>(), N, E.st);
-      combo(B.P1(0), N, m, R.q.as<double>(), m, 1, kp, N, 1.0, 0.0, ptmp.as<double>(), N, E.st);
+      combo(B.V(0), N, m, R.q.as<double>(), R.ldq, 1, kp, N, 1.0, 0.0, vtmp.as<double>(), N, E.st);
+      combo(B.P1(0), N, m, R.q.as<double>(), R.ldq, 1, kp, N, 1.0, 0.0, ptmp.as<double>(), N, E.st);
       RID_HIP(hipMemcpyAsync(B.V(0), vtmp.p, sizeof(double) * kp * N, hipMemcpyDeviceToDevice, E.st));
       RID_HIP(hipMemcpyAsync(B.P1(0), ptmp.p, sizeof(double) * kp * N, hipMemcpyDeviceToDevice, E.st));
       std::vector<double> wk(kp);

@@ -61,6 +61,11 @@ void scale_copy(const double* src, long n, double alpha, double* dst, hipStream_
 // Jacobi in one workgroup; a is overwritten.  w[m] ascending, q (m x m,
 // row-major, q[i * m + j] = component i of eigenvector j); work >= m*m + m.
 void small_eigh(double* a, int m, int lda, double* w, double* q, double* work, hipStream_t s);
+// The k lowest eigenpairs of symmetric a (m x m, lda; destroyed): w[k]
+// ascending, q[i * ldq + t] = component i of eigenvector t.  work >=
+// small_syevx_work(m, k) doubles.
+size_t small_syevx_work(int m, int k);
+void small_syevx(double* a, int m, int lda, int k, double* w, double* q, int ldq, double* work, hipStream_t s);
 // Cholesky a = L L^T in place (lower triangle, upper zeroed); info[0] = 0 on
 // success, j+1 if the j-th pivot is not positive.
 void small_chol(double* a, int m, int lda, int* info, hipStream_t s);
@@ -72,6 +77,14 @@ void small_lu_solve(double* mats, double* rhs, int m, int nb, hipStream_t s);
 // C (m x n) = alpha * op(A) op(B) + beta * C, row-major, op = transpose if t*.
 void small_gemm(int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
                 double beta, double* C, int ldc, hipStream_t s);
+// G = L^{-1} for lower-triangular L (m x m).
+void small_trinv_lower(const double* L, int m, int ldl, double* G, int ldg, hipStream_t s);
+// mats_b = t - sh_b^2 w for b < nb (m x m each, contiguous).
+void build_schur(const double* t, int ldt, const double* w, int ldw, int m, const double* sh, int nb, double* mats,
+                 hipStream_t s);
+// out_b = x_b + sh_b y_b for nb rows of length m.
+void rows_axpy(const double* x, int ldx, const double* y, int ldy, const double* sh, int nb, int m, double* out,
+               int ldo, hipStream_t s);
 // Symmetrise in place: a = (a + a^T) / 2 over the leading m x m block.
 void small_symmetrize(double* a, int m, int lda, hipStream_t s);
 // Build shifted systems for the inner solves: for b < nb,

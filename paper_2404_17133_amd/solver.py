@@ -81,6 +81,22 @@ class Context:
             raise RidError(s, B.lib.rid_last_error(None).decode())
         self.handle = h
 
+    def profile(self, on: bool = True):
+        """Enable or disable per-kernel-family launch timing."""
+        self.check(B.lib.rid_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """Per-family totals since the last read: {name: dict(launches, ms, flops, bytes)}."""
+        cap = 64
+        arr = (B.rid_kernel_stat * cap)()
+        n = ctypes.c_int32()
+        self.check(B.lib.rid_profile_read(self.handle, arr, cap, ctypes.byref(n)))
+        out = {}
+        for i in range(min(n.value, cap)):
+            s = arr[i]
+            out[s.name.decode()] = dict(launches=int(s.launches), ms=s.total_ms, flops=s.flops, bytes=s.bytes)
+        return out
+
     def check(self, s: int, ok=(B.RID_OK,)):
         if s not in ok:
             raise RidError(s, B.lib.rid_last_error(self.handle).decode())

@@ -81,6 +81,30 @@ def cpu_baseline(p, n_mv_per_step, roots_per_step, naux_sample=200):
     }
 
 
+def measured_traffic(family: str, dtype: str):
+    """Calibrated HBM bytes per launch of `family` from the committed counter
+    summary, or None when the GEMM source changed since the counters were
+    taken (or no summary exists)."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", "exch_contractions_c2_mixed_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "paper_2404_17133_amd"))
+    from profsum import gemm_source_hash
+
+    text = open(path).read()
+    m = re.search(r"GEMM source hash: (\w+)", text)
+    if not m or m.group(1) != gemm_source_hash():
+        return None
+    t = {"f32": "float", "bf16": "bf16_t", "f64": "double"}[dtype]
+    fam = family[4:] if family.startswith("ris_") else family
+    for line in text.splitlines():
+        if line.startswith("| gemm_nt<%s,128x128," % t) and line.split("|")[1].strip().endswith("[%s]" % fam):
+            return float(line.split("|")[5]) * 1e9
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +114,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1, help="steps of the FP64 GPU comparison (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB of a plain device copy (x * 1.0 on float32) run before timing, so that "
+                         "hardware-counter runs can calibrate byte counters against a known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
@@ -107,6 +134,13 @@ def main():
     pm = make_dipoles(p, 3)
     torch.cuda.synchronize()
     log("inputs generated on the device in %.1f s" % (time.time() - t0))
+    if args.copy_probe > 0:
+        xs = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+        torch.cuda.synchronize()
+        ys = xs * 1.0  # reads and writes copy_probe MiB
+        torch.cuda.synchronize()
+        del xs, ys
+        log("copy probe: %d MiB read + %d MiB written" % (args.copy_probe, args.copy_probe))
     ctx = rid.Context(0)
     prob = rid.Problem.from_synth(ctx, p)
     k = args.k
@@ -150,8 +184,10 @@ def main():
     avg_ms = st["ms"] / st["launches"]
     dtype = "f32" if not fam.startswith("ris_") else "bf16"
     achieved = st["flops"] / st["launches"] / (avg_ms * 1e-3) / 1e12
+    traffic = measured_traffic(fam, dtype)
     roofline = {"bound": "mfma", "kernel": fam, "achieved": round(achieved, 2), "peak": PEAK[dtype],
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK[dtype], 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK[dtype], 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": st["bytes"] / st["launches"],
                 "avg_launch_ms": round(avg_ms, 4), "launches": st["launches"],
                 "flops_per_launch": st["flops"] / st["launches"]}
 

@@ -216,7 +216,7 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
     {
       ProfScope ps(ctx, (pre + "coul_fwd").c_str(), 2.0 * nvec * naux_j * (double)n,
                    esz * ((double)naux_j * n + (double)nvec * n) + asz * nsplit * nvec * naux_j);
-      gemm_nt<G>(g, 1, nsplit, st, 1);
+      gemm_nt<G>(g, 1, nsplit, st, 1, GF_COUL);
     }
     reduce_splits<Acc>(w.tpart.as<Acc>(), nsplit, (long)nvec * naux_j, (long)nvec * naux_j, w.t64.as<double>(), st);
     t64 = w.t64.as<double>();
@@ -275,7 +275,7 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
         g.mode = GEMM_STORE;
         ProfScope ps(ctx, (pre + "exch_s").c_str(), 2.0 * no_a * (double)nvec * nv_a * no_a * pcc,
                      esz * ((double)pcc * no_a * no_a + (double)nvec * nv_a * no_a + (double)pcc * s_per_p));
-        gemm_nt<G>(g, pcc, 1, st);
+        gemm_nt<G>(g, pcc, 1, st, -1, GF_EXCH_S);
       }
       {  // W += sum_P S^P B^P_ab (window)
         GemmParams g{};
@@ -299,7 +299,7 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
         ProfScope ps(ctx, (pre + "exch_w").c_str(), 2.0 * rows * (double)nv_a * nv_a * pcc,
                      esz * ((double)pcc * s_per_p + (double)pcc * nv_a * nv_a) +
                          asz * part_elems * nsub * (mode == GEMM_PARTIAL_ADD ? 2.0 : 1.0));
-        gemm_nt<G>(g, 1, nsub, st);
+        gemm_nt<G>(g, 1, nsub, st, -1, GF_EXCH_W);
       }
       if (pair) {
         {  // Q^P = B^P_ia (window) x Xa^T
@@ -322,7 +322,7 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
           g.mode = GEMM_STORE;
           ProfScope ps(ctx, (pre + "exch_q").c_str(), 2.0 * no_a * (double)nvec * no_a * nv_a * pcc,
                        esz * ((double)pcc * no_a * nv_a + (double)nvec * no_a * nv_a + (double)pcc * q_per_p));
-          gemm_nt<G>(g, pcc, 1, st);
+          gemm_nt<G>(g, pcc, 1, st, -1, GF_EXCH_Q);
         }
         {  // W' += sum_P Q^P B^P_ja (window), B_ja read from the transposed copy
           GemmParams g{};
@@ -346,7 +346,7 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
           ProfScope ps(ctx, (pre + "exch_wp").c_str(), 2.0 * rows * (double)nv_a * no_a * pcc,
                        esz * ((double)pcc * q_per_p + (double)pcc * nv_a * no_a) +
                            asz * part_elems * nsub * (mode == GEMM_PARTIAL_ADD ? 2.0 : 1.0));
-          gemm_nt<G>(g, 1, nsub, st);
+          gemm_nt<G>(g, 1, nsub, st, -1, GF_EXCH_WP);
         }
       }
     }

@@ -78,7 +78,7 @@ struct Atom<bf16_t> {
   __device__ static inline uint16_t out(acc_t v) { return f32_to_bf16_bits(v); }
 };
 
-template <typename T, int BM, int BN, int WM, int WN, bool VEC>
+template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmParams p) {
   using At = Atom<T>;
   using E_t = typename At::elem_t;
@@ -253,14 +253,26 @@ struct Cfgs<bf16_t> {
   static constexpr TileCfg c[3] = {{128, 128}, {64, 64}, {128, 64}};
 };
 
+template <typename T, int BM, int BN, int WM, int WN, int FAM>
+void launch_fam(const GemmParams& p, dim3 grid, bool vec, hipStream_t stream) {
+  if (vec)
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, true, FAM>), grid, dim3(256), 0, stream, p);
+  else
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, false, FAM>), grid, dim3(256), 0, stream, p);
+}
+
 template <typename T, int BM, int BN, int WM, int WN>
-void launch_cfg(const GemmParams& p, int nz, int nsplit, bool vec, hipStream_t stream) {
+void launch_cfg(const GemmParams& p, int nz, int nsplit, bool vec, hipStream_t stream, int family) {
   const int tiles = ceil_div(p.M, BM) * ceil_div(p.N, BN);
   dim3 grid(tiles, nz, nsplit);
-  if (vec)
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, true>), grid, dim3(256), 0, stream, p);
-  else
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, false>), grid, dim3(256), 0, stream, p);
+  switch (family) {
+    case GF_COUL: launch_fam<T, BM, BN, WM, WN, GF_COUL>(p, grid, vec, stream); break;
+    case GF_EXCH_S: launch_fam<T, BM, BN, WM, WN, GF_EXCH_S>(p, grid, vec, stream); break;
+    case GF_EXCH_W: launch_fam<T, BM, BN, WM, WN, GF_EXCH_W>(p, grid, vec, stream); break;
+    case GF_EXCH_Q: launch_fam<T, BM, BN, WM, WN, GF_EXCH_Q>(p, grid, vec, stream); break;
+    case GF_EXCH_WP: launch_fam<T, BM, BN, WM, WN, GF_EXCH_WP>(p, grid, vec, stream); break;
+    default: launch_fam<T, BM, BN, WM, WN, GF_GENERIC>(p, grid, vec, stream); break;
+  }
 }
 
 template <typename T>
@@ -281,7 +293,7 @@ void gemm_config_tile(int cfg, int* bm, int* bn) {
 }
 
 template <typename T>
-void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int cfg) {
+void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int cfg, int family) {
   if (p.M <= 0 || p.N <= 0 || nz <= 0 || nsplit <= 0) return;
   RID_CHECK(p.np >= 1 && p.pps >= 1 && p.nz2 >= 1, RID_ERR_INTERNAL, "gemm: bad batch counts");
   RID_CHECK((long)nsplit * p.pps >= p.np, RID_ERR_INTERNAL, "gemm: splits do not cover batches");
@@ -297,16 +309,16 @@ void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int cf
     cfg = (t128 >= 512) ? 0 : 1;
   }
   switch (cfg) {
-    case 0: launch_cfg<T, 128, 128, 64, 64>(p, nz, nsplit, vec, stream); break;
-    case 1: launch_cfg<T, 64, 64, 32, 32>(p, nz, nsplit, vec, stream); break;
-    default: launch_cfg<T, 128, 64, 64, 32>(p, nz, nsplit, vec, stream); break;
+    case 0: launch_cfg<T, 128, 128, 64, 64>(p, nz, nsplit, vec, stream, family); break;
+    case 1: launch_cfg<T, 64, 64, 32, 32>(p, nz, nsplit, vec, stream, family); break;
+    default: launch_cfg<T, 128, 64, 64, 32>(p, nz, nsplit, vec, stream, family); break;
   }
   RID_HIP(hipGetLastError());
 }
 
-template void gemm_nt<double>(const GemmParams&, int, int, hipStream_t, int);
-template void gemm_nt<float>(const GemmParams&, int, int, hipStream_t, int);
-template void gemm_nt<bf16_t>(const GemmParams&, int, int, hipStream_t, int);
+template void gemm_nt<double>(const GemmParams&, int, int, hipStream_t, int, int);
+template void gemm_nt<float>(const GemmParams&, int, int, hipStream_t, int, int);
+template void gemm_nt<bf16_t>(const GemmParams&, int, int, hipStream_t, int, int);
 template int gemm_num_configs<double>();
 template int gemm_num_configs<float>();
 template int gemm_num_configs<bf16_t>();

@@ -16,6 +16,10 @@ namespace rid {
 
 enum GemmMode { GEMM_STORE = 0, GEMM_PARTIAL_SET = 1, GEMM_PARTIAL_ADD = 2 };
 
+// Contraction family of a launch.  Each family gets its own kernel symbol
+// (same code) so that profilers report the families separately.
+enum GemmFamily { GF_GENERIC = 0, GF_COUL = 1, GF_EXCH_S = 2, GF_EXCH_W = 3, GF_EXCH_Q = 4, GF_EXCH_WP = 5 };
+
 struct GemmParams {
   const void* A;
   const void* B;
@@ -39,7 +43,7 @@ struct bf16_t {};
 // output is written in the accumulator type (double for T = double, float
 // otherwise); for GEMM_STORE it is written in T.
 template <typename T>
-void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int tile_cfg = -1);
+void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int tile_cfg = -1, int family = GF_GENERIC);
 
 // Number of tile configurations available for T (for the autotuner).
 template <typename T>

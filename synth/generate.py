@@ -212,7 +212,10 @@ def make_problem(no: int, nv: int, naux: int, naux_ris: int = 0,
 
     b_ia = _normal_tensor(seed, _STREAM_B_IA, (naux, no, nv), dev)
     g2 = b_ia.reshape(naux, no * nv)
-    smax2 = float(torch.linalg.eigvalsh(g2 @ g2.T)[-1])
+    # the (Naux x Naux) Gram matrices are formed on the device and
+    # diagonalised on the host, so that the result does not depend on the
+    # device's eigensolver
+    smax2 = float(torch.linalg.eigvalsh((g2 @ g2.T).cpu())[-1])
     scale = math.sqrt(coupling / smax2) if smax2 > 0 else 0.0
     b_ia.mul_(scale)
     b_ij = _normal_tensor(seed, _STREAM_B_IJ, (naux, no, no), dev, symmetric=True).mul_(scale)
@@ -232,8 +235,8 @@ def make_problem(no: int, nv: int, naux: int, naux_ris: int = 0,
         for blk in (b_ia, b_ij, b_ab):
             m = blk.reshape(naux, -1)
             gram += m @ m.T
-        _, vecs = torch.linalg.eigh(gram)
-        rot = torch.flip(vecs[:, naux - naux_ris:], dims=[1])  # descending
+        _, vecs = torch.linalg.eigh(gram.cpu())
+        rot = torch.flip(vecs[:, naux - naux_ris:], dims=[1]).to(dev)  # descending
         # deterministic sign: the largest-magnitude entry of each column > 0
         idx = torch.argmax(rot.abs(), dim=0)
         sgn = torch.sign(rot[idx, torch.arange(naux_ris, device=dev)])

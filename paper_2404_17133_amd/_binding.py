@@ -11,7 +11,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librid.so")
+# RID_LIBRARY selects another build of the same library (for side-by-side
+# measurements); the default is the in-tree build.
+LIB_PATH = os.environ.get("RID_LIBRARY") or os.path.join(HERE, "librid.so")
 
 RID_OK = 0
 RID_WARN_NOT_CONVERGED = 1

@@ -9,7 +9,7 @@
 #include <stdexcept>
 #include <string>
 
-#include "../../include/rid.h"
+#include "rid.h"
 
 namespace rid {
 

@@ -15,6 +15,7 @@
 // combine kernel reduces in f64.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "core.hpp"
 #include "gemm.hpp"
@@ -161,6 +162,115 @@ struct AccOf<double> {
   typedef double type;
 };
 
+// Workgroup slots of the chip per GEMM tile configuration: 256 CUs times the
+// workgroups one CU holds at the kernel's register and LDS use
+// (cfg 0 = 128x128, 1 = 64x64, 2 = 128x64).
+template <typename E>
+int gemm_slots(int cfg = 0) {
+  static const int f64[3] = {256, 512, 256};
+  static const int f32[3] = {512, 1024, 512};
+  return sizeof(E) == 8 ? f64[cfg] : f32[cfg];
+}
+
+// Split a reduction over np batches (each K deep) into nsub launches of pps
+// batches so that the last round of workgroups is as full as possible, while
+// keeping each workgroup's reduction deep enough to amortise its epilogue.
+struct SplitPlan {
+  int nsub, pps;
+};
+
+SplitPlan choose_splits(long tiles, int np, int K, int slots, int max_splits = 64) {
+  SplitPlan best{1, np};
+  double best_score = -1.0;
+  for (int ns = 1; ns <= std::min(np, max_splits); ++ns) {
+    const int pps = ceil_div(np, ns);
+    const int ns2 = ceil_div(np, pps);
+    const long total = tiles * ns2;
+    const long rounds = (total + slots - 1) / slots;
+    const double eff = (double)total / (double)(rounds * slots);
+    const double depth = (double)pps * K;
+    const double score = eff * depth / (depth + 512.0);
+    if (score > best_score + 1e-9) {
+      best_score = score;
+      best = SplitPlan{ns2, pps};
+    }
+  }
+  return best;
+}
+
+struct GemmChoice {
+  int cfg, nsub, pps;
+};
+
+// Tile configuration and split plan of one launch shape.  reduction: the
+// launch sums np batches (split over nsub workgroups per tile); otherwise np
+// is 1 and nz independent batches run.
+template <typename E>
+GemmChoice plan_for(int cfg, long M, long N, int nz, int np, int K, bool reduction) {
+  static const int bm[3] = {128, 64, 128}, bn[3] = {128, 64, 64};
+  const long tiles = ceil_div_l(M, bm[cfg]) * ceil_div_l(N, bn[cfg]) * nz;
+  if (!reduction) return GemmChoice{cfg, 1, np};
+  const SplitPlan sp = choose_splits(tiles, np, K, gemm_slots<E>(cfg));
+  return GemmChoice{cfg, sp.nsub, sp.pps};
+}
+
+bool autotune_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("RID_AUTOTUNE");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+// Autotuner: the first launch of a shape times every tile configuration
+// (each with its own split plan) and keeps the fastest for the context.
+// `launch` must be idempotent (GEMM_STORE or GEMM_PARTIAL_SET), so the
+// candidate runs leave the same result as a single run of the winner.
+template <typename E, typename F>
+GemmChoice tuned(rid_context* ctx, int family, long M, long N, int nz, int np, int K, bool reduction, F&& launch) {
+  const TuneKey key{family, (int)sizeof(E), M, N, nz, np, K};
+  auto it = ctx->tune.find(key);
+  if (it != ctx->tune.end()) {
+    const GemmChoice ch{it->second.cfg, it->second.nsub, it->second.pps};
+    launch(ch);
+    return ch;
+  }
+  GemmChoice best = plan_for<E>(0, M, N, nz, np, K, reduction);
+  if (!autotune_enabled()) {
+    // without tuning: the 128x128 tile when it fills the chip, else 64x64
+    static const int bm = 128;
+    const long t128 = ceil_div_l(M, bm) * ceil_div_l(N, bm) * nz * best.nsub;
+    if (t128 < gemm_slots<E>(0) / 2) best = plan_for<E>(1, M, N, nz, np, K, reduction);
+    launch(best);
+  } else {
+    hipEvent_t a, b;
+    RID_HIP(hipEventCreate(&a));
+    RID_HIP(hipEventCreate(&b));
+    float best_ms = 1e30f;
+    GemmChoice last{};
+    for (int cfg = 0; cfg < 3; ++cfg) {
+      const GemmChoice ch = plan_for<E>(cfg, M, N, nz, np, K, reduction);
+      launch(ch);  // warm
+      RID_HIP(hipEventRecord(a, ctx->stream));
+      launch(ch);
+      RID_HIP(hipEventRecord(b, ctx->stream));
+      RID_HIP(hipEventSynchronize(b));
+      float ms = 0.0f;
+      RID_HIP(hipEventElapsedTime(&ms, a, b));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = ch;
+      }
+      last = ch;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (last.cfg != best.cfg) launch(best);
+  }
+  ctx->tune[key] = TuneVal{best.cfg, best.nsub, best.pps};
+  return best;
+}
+
 template <typename E>
 void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, const double* x, double* y,
                   double* y2) {
@@ -189,11 +299,8 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
   const int naux_j = ov.naux_j;
   double* t64 = nullptr;
   if (naux_j > 0) {
-    const long tiles = (long)ceil_div(nvec, 64) * ceil_div(naux_j, 64);
-    int nsplit = (int)std::min<long>(no, std::max<long>(1, (1024 + tiles - 1) / tiles));
-    const int pps = ceil_div(no, nsplit);
-    nsplit = ceil_div(no, pps);
-    w.tpart.ensure(sizeof(Acc) * (size_t)nsplit * nvec * naux_j);
+    // partial buffer sized for the largest split count any plan can pick
+    w.tpart.ensure(sizeof(Acc) * (size_t)std::min(no, 64) * nvec * naux_j);
     w.t64.ensure(sizeof(double) * (size_t)nvec * naux_j);
     GemmParams g{};
     g.A = w.xc.p;
@@ -203,7 +310,6 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
     g.N = naux_j;
     g.K = nv;
     g.np = no;
-    g.pps = pps;
     g.nz2 = 1;
     g.lda = n;
     g.ldb = n;
@@ -213,11 +319,16 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
     g.sCs = (long)nvec * naux_j;
     g.alpha = 1.0;
     g.mode = GEMM_PARTIAL_SET;
+    GemmChoice ch;
     {
       ProfScope ps(ctx, (pre + "coul_fwd").c_str(), 2.0 * nvec * naux_j * (double)n,
-                   esz * ((double)naux_j * n + (double)nvec * n) + asz * nsplit * nvec * naux_j);
-      gemm_nt<G>(g, 1, nsplit, st, 1, GF_COUL);
+                   esz * ((double)naux_j * n + (double)nvec * n));
+      ch = tuned<E>(ctx, GF_COUL, nvec, naux_j, 1, no, nv, true, [&](const GemmChoice& c) {
+        g.pps = c.pps;
+        gemm_nt<G>(g, 1, c.nsub, st, c.cfg, GF_COUL);
+      });
     }
+    const int nsplit = ch.nsub;
     reduce_splits<Acc>(w.tpart.as<Acc>(), nsplit, (long)nvec * naux_j, (long)nvec * naux_j, w.t64.as<double>(), st);
     t64 = w.t64.as<double>();
     w.jbuf.ensure(sizeof(double) * nvec * n);
@@ -238,23 +349,22 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
     const long q_per_p = (long)no_a * nvec * no_a;
     const long per_p = std::max(s_per_p, pair ? q_per_p : 0L);
     const long target = 256L << 20;  // bytes of intermediate per chunk
-    int pc = (int)std::max<long>(1, std::min<long>(nk, target / std::max<long>(1, per_p * (long)sizeof(E))));
-    const long tiles128 = ceil_div_l(rows, 128) * ceil_div_l(nv_a, 128);
-    int nsub = (int)std::max<long>(1, std::min<long>(64, (1024 + tiles128 - 1) / tiles128));
-    nsub = std::min(nsub, pc);
-    const int pps = ceil_div(pc, nsub);
-    nsub = ceil_div(pc, pps);
-    ns_w = nsub;
-    w.s.ensure(sizeof(E) * (size_t)pc * s_per_p);
-    w.wpart.ensure(sizeof(Acc) * (size_t)nsub * part_elems);
-    if (pair) {
-      ns_wp = nsub;
-      w.q.ensure(sizeof(E) * (size_t)pc * q_per_p);
-      w.wppart.ensure(sizeof(Acc) * (size_t)nsub * part_elems);
+    const int pc = (int)std::max<long>(1, std::min<long>(nk, target / std::max<long>(1, per_p * (long)sizeof(E))));
+    int max_splits = 1;
+    for (int cfg = 0; cfg < 3; ++cfg) {
+      max_splits = std::max(max_splits, plan_for<E>(cfg, rows, nv_a, 1, pc, nv_a, true).nsub);
+      max_splits = std::max(max_splits, plan_for<E>(cfg, rows, nv_a, 1, pc, no_a, true).nsub);
     }
+    w.s.ensure(sizeof(E) * (size_t)pc * s_per_p);
+    w.wpart.ensure(sizeof(Acc) * (size_t)max_splits * part_elems);
+    if (pair) {
+      w.q.ensure(sizeof(E) * (size_t)pc * q_per_p);
+      w.wppart.ensure(sizeof(Acc) * (size_t)max_splits * part_elems);
+    }
+    GemmChoice cw{}, cwp{};
     for (int c0 = 0; c0 < nk; c0 += pc) {
       const int pcc = std::min(pc, nk - c0);
-      const int mode = c0 == 0 ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
+      const bool first = c0 == 0;
       {  // S^P = B^P_ij (window) x Xt
         GemmParams g{};
         g.A = ov.b_ij + (long)c0 * no * no + (long)i0 * no + i0;
@@ -275,7 +385,9 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
         g.mode = GEMM_STORE;
         ProfScope ps(ctx, (pre + "exch_s").c_str(), 2.0 * no_a * (double)nvec * nv_a * no_a * pcc,
                      esz * ((double)pcc * no_a * no_a + (double)nvec * nv_a * no_a + (double)pcc * s_per_p));
-        gemm_nt<G>(g, pcc, 1, st, -1, GF_EXCH_S);
+        tuned<E>(ctx, GF_EXCH_S, no_a, (long)nvec * nv_a, pcc, 1, no_a, false, [&](const GemmChoice& ch) {
+          gemm_nt<G>(g, pcc, 1, st, ch.cfg, GF_EXCH_S);
+        });
       }
       {  // W += sum_P S^P B^P_ab (window)
         GemmParams g{};
@@ -286,7 +398,6 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
         g.N = nv_a;
         g.K = nv_a;
         g.np = pcc;
-        g.pps = pps;
         g.nz2 = 1;
         g.lda = nv_a;
         g.ldb = nv;
@@ -295,11 +406,18 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
         g.sBp = (long)nv * nv;
         g.sCs = part_elems;
         g.alpha = 1.0;
-        g.mode = mode;
+        g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
         ProfScope ps(ctx, (pre + "exch_w").c_str(), 2.0 * rows * (double)nv_a * nv_a * pcc,
                      esz * ((double)pcc * s_per_p + (double)pcc * nv_a * nv_a) +
-                         asz * part_elems * nsub * (mode == GEMM_PARTIAL_ADD ? 2.0 : 1.0));
-        gemm_nt<G>(g, 1, nsub, st, -1, GF_EXCH_W);
+                         asz * part_elems * (first ? 1.0 : 2.0));
+        auto launch = [&](const GemmChoice& ch) {
+          g.pps = ch.pps;
+          gemm_nt<G>(g, 1, ch.nsub, st, ch.cfg, GF_EXCH_W);
+        };
+        if (first)
+          cw = tuned<E>(ctx, GF_EXCH_W, rows, nv_a, 1, pcc, nv_a, true, launch);
+        else
+          launch(cw);
       }
       if (pair) {
         {  // Q^P = B^P_ia (window) x Xa^T
@@ -322,7 +440,9 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
           g.mode = GEMM_STORE;
           ProfScope ps(ctx, (pre + "exch_q").c_str(), 2.0 * no_a * (double)nvec * no_a * nv_a * pcc,
                        esz * ((double)pcc * no_a * nv_a + (double)nvec * no_a * nv_a + (double)pcc * q_per_p));
-          gemm_nt<G>(g, pcc, 1, st, -1, GF_EXCH_Q);
+          tuned<E>(ctx, GF_EXCH_Q, no_a, (long)nvec * no_a, pcc, 1, nv_a, false, [&](const GemmChoice& ch) {
+            gemm_nt<G>(g, pcc, 1, st, ch.cfg, GF_EXCH_Q);
+          });
         }
         {  // W' += sum_P Q^P B^P_ja (window), B_ja read from the transposed copy
           GemmParams g{};
@@ -333,7 +453,6 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
           g.N = nv_a;
           g.K = no_a;
           g.np = pcc;
-          g.pps = pps;
           g.nz2 = 1;
           g.lda = no_a;
           g.ldb = no;
@@ -342,14 +461,23 @@ void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, cons
           g.sBp = (long)nv * no;
           g.sCs = part_elems;
           g.alpha = 1.0;
-          g.mode = mode;
+          g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
           ProfScope ps(ctx, (pre + "exch_wp").c_str(), 2.0 * rows * (double)nv_a * no_a * pcc,
                        esz * ((double)pcc * q_per_p + (double)pcc * nv_a * no_a) +
-                           asz * part_elems * nsub * (mode == GEMM_PARTIAL_ADD ? 2.0 : 1.0));
-          gemm_nt<G>(g, 1, nsub, st, -1, GF_EXCH_WP);
+                           asz * part_elems * (first ? 1.0 : 2.0));
+          auto launch = [&](const GemmChoice& ch) {
+            g.pps = ch.pps;
+            gemm_nt<G>(g, 1, ch.nsub, st, ch.cfg, GF_EXCH_WP);
+          };
+          if (first)
+            cwp = tuned<E>(ctx, GF_EXCH_WP, rows, nv_a, 1, pcc, no_a, true, launch);
+          else
+            launch(cwp);
         }
       }
     }
+    ns_w = cw.nsub;
+    ns_wp = pair ? cwp.nsub : 0;
   }
 
   // 4. combine in f64

@@ -34,6 +34,25 @@ struct Profiler {
   ~Profiler();
 };
 
+// Autotuner cache: launch shape -> chosen tile configuration and split plan.
+struct TuneKey {
+  int family, esz;
+  long M, N;
+  int nz, np, K;
+  bool operator<(const TuneKey& o) const {
+    if (family != o.family) return family < o.family;
+    if (esz != o.esz) return esz < o.esz;
+    if (M != o.M) return M < o.M;
+    if (N != o.N) return N < o.N;
+    if (nz != o.nz) return nz < o.nz;
+    if (np != o.np) return np < o.np;
+    return K < o.K;
+  }
+};
+struct TuneVal {
+  int cfg, nsub, pps;
+};
+
 }  // namespace rid
 
 struct rid_context {
@@ -44,6 +63,7 @@ struct rid_context {
   std::string last_error;
   std::mutex mu;  // guards allocator use from the server thread
   rid::Profiler prof;
+  std::map<rid::TuneKey, rid::TuneVal> tune;
 };
 
 namespace rid {

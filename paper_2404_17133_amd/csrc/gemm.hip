@@ -4,8 +4,8 @@
 // WM x WN sub-tile made of MFMA atoms (32x32 for f32/bf16, 16x16 for f64).
 // Every K stage moves 128 bytes of K per operand row (32 f32, 16 f64, 64
 // bf16) from global memory to LDS, double-buffered with one barrier per
-// stage: the next stage's global loads are issued before the current stage's
-// MFMAs and written to the other LDS buffer afterwards.  LDS rows are padded
+// stage.  (Measured on gfx950: a second stage of register prefetch and an
+// XCD-aware re-mapping of workgroups to tiles did not help at these shapes.)  LDS rows are padded
 // by 16 bytes (stride 144 B) so that the 16-byte fragment reads of 16
 // consecutive rows hit distinct banks.  The K order inside a stage is
 // permuted so that each lane reads one contiguous slice per operand row: lane
@@ -78,8 +78,19 @@ struct Atom<bf16_t> {
   __device__ static inline uint16_t out(acc_t v) { return f32_to_bf16_bits(v); }
 };
 
+// Two workgroups per CU (two waves per SIMD) for the 4-byte and 2-byte
+// element types; the FP64 128x128 tile needs the whole register file.
+template <typename T>
+struct MinBlocks {
+  static constexpr int value = 2;
+};
+template <>
+struct MinBlocks<double> {
+  static constexpr int value = 1;
+};
+
 template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmParams p) {
+__global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmParams p) {
   using At = Atom<T>;
   using E_t = typename At::elem_t;
   using V_t = typename At::vec_t;
@@ -107,11 +118,11 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmParams p) {
   const int tiles_m = (p.M + BM - 1) / BM;
   const int tm = blockIdx.x % tiles_m;
   const int tn = blockIdx.x / tiles_m;
+  const int z = blockIdx.y;
+  const int split = blockIdx.z;
   const int m0 = tm * BM;
   const int n0 = tn * BN;
-  const int z = blockIdx.y;
   const int z1 = z / p.nz2, z2 = z % p.nz2;
-  const int split = blockIdx.z;
   const int pbeg = split * p.pps;
   const int pend = min(p.np, pbeg + p.pps);
   const E_t* Ab = reinterpret_cast<const E_t*>(p.A) + z1 * p.sA1 + z2 * p.sA2;
@@ -121,9 +132,8 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmParams p) {
 
   const int kc = tid & 7;
   const int rbase = tid >> 3;
-  uint4 pre[CPT];
 
-  auto gload = [&](int t) {
+  auto gload = [&](int t, uint4 (&pre)[CPT]) {
     const int pp = pbeg + t / nkt;
     const int k = (t % nkt) * BK + kc * VW;
 #pragma unroll
@@ -150,7 +160,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmParams p) {
       }
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const uint4 (&pre)[CPT]) {
 #pragma unroll
     for (int i = 0; i < CPT; ++i) lds[buf][(rbase + 32 * i) * RS + kc] = pre[i];
   };
@@ -168,14 +178,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmParams p) {
 #pragma unroll
       for (int r = 0; r < At::NACC; ++r) acc[i][j][r] = acc_t(0);
 
-  if (nstage > 0) {
-    gload(0);
-    lstore(0);
-  }
-  __syncthreads();
-  for (int t = 0; t < nstage; ++t) {
-    const int buf = t & 1;
-    if (t + 1 < nstage) gload(t + 1);
+  auto compute = [&](int buf) {
     V_t fa[AMN][SL];
     V_t fb[ANN][SL];
 #pragma unroll
@@ -196,7 +199,20 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmParams p) {
       for (int i = 0; i < AMN; ++i)
 #pragma unroll
         for (int j = 0; j < ANN; ++j) acc[i][j] = At::mma(At::op(fa[i], s), At::op(fb[j], s), acc[i][j]);
-    if (t + 1 < nstage) lstore((t + 1) & 1);
+  };
+
+  // One stage in flight: the next stage's global loads are issued before the
+  // MFMAs of the current stage and written to the other LDS buffer after them.
+  uint4 pa[CPT];
+  if (nstage > 0) {
+    gload(0, pa);
+    lstore(0, pa);
+  }
+  __syncthreads();
+  for (int t = 0; t < nstage; ++t) {
+    if (t + 1 < nstage) gload(t + 1, pa);
+    compute(t & 1);
+    if (t + 1 < nstage) lstore((t + 1) & 1, pa);
     __syncthreads();
   }
 

@@ -255,3 +255,26 @@ def dense_hessians(eps_occ, eps_vir, eri, a_x, occ_active=None, vir_active=None)
                     amat[ia, jb] = A
                     bmat[ia, jb] = B
     return amat, bmat
+
+
+def sampled_entries(b_ia_rows_i, b_ia_cols_a, b_ij_rows_i, b_ab_cols_a, b_ia, a_x, de_ia, x_cube, i, a):
+    """((A+B) x)_ia and ((A-B) x)_ia for one output entry, from Eq. hessian.
+
+    For full-size checks where the whole product is too costly: every term is
+    summed straight from its definition over the auxiliary index.
+      b_ia_rows_i = B^P_{i b}  (naux, nv)    b_ia_cols_a = B^P_{j a}  (naux, no)
+      b_ij_rows_i = B^P_{i j}  (naux, no)    b_ab_cols_a = B^P_{b a}  (naux, nv)
+      b_ia: the full (naux, no, nv) tensor (for the Coulomb term)
+      x_cube: (no, nv) vector, de_ia = eps_a - eps_i.
+    K x   = sum_P B^P_ia sum_jb B^P_jb x_jb
+    W x   = sum_P sum_jb B^P_ij B^P_ba x_jb
+    W' x  = sum_P sum_jb B^P_ib B^P_ja x_jb
+    """
+    naux = b_ia.shape[0]
+    t = b_ia.reshape(naux, -1) @ x_cube.reshape(-1)          # sum_jb B^P_jb x_jb
+    kx = float(b_ia[:, i, a] @ t)
+    wx = float(np.sum((b_ij_rows_i @ x_cube) * b_ab_cols_a))     # sum_P sum_b (sum_j B_ij x_jb) B_ba
+    wpx = float(np.sum((b_ia_rows_i @ x_cube.T) * b_ia_cols_a))  # sum_P sum_j (sum_b B_ib x_jb) B_ja
+    apb = de_ia * x_cube[i, a] + 4.0 * kx - a_x * (wx + wpx)
+    amb = de_ia * x_cube[i, a] - a_x * (wx - wpx)
+    return apb, amb

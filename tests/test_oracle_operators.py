@@ -179,3 +179,17 @@ def test_a_minus_b_and_a_plus_b_positive_definite_at_small_config(ris):
     apb, amb = (ops.apply_tpm if ris else ops.apply_apb_amb)(op, eye)
     assert np.linalg.eigvalsh(apb).min() > 0.0
     assert np.linalg.eigvalsh(amb).min() > 0.0
+
+
+def test_sampled_entries_match_full_products():
+    op = tiny(no=4, nv=7, naux=9)
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((op.n, 1))
+    apb, amb = ops.apply_apb_amb(op, x)
+    xc = x[:, 0].reshape(op.no, op.nv)
+    de = op.delta_eps().reshape(op.no, op.nv)
+    for i, a in ((0, 0), (3, 6), (2, 1)):
+        p, m = ops.sampled_entries(op.b_ia[:, i, :], op.b_ia[:, :, a], op.b_ij[:, i, :], op.b_ab[:, :, a],
+                                   op.b_ia, op.a_x, de[i, a], xc, i, a)
+        assert abs(p - apb[i * op.nv + a, 0]) < 1e-13
+        assert abs(m - amb[i * op.nv + a, 0]) < 1e-13

@@ -122,11 +122,12 @@ typedef struct {
   const void* b_ia_dev;      /* (naux, no, nv) */
   const void* b_ij_dev;      /* (naux, no, no) symmetric slices */
   const void* b_ab_dev;      /* (naux, nv, nv) symmetric slices */
-  int32_t b_dtype;           /* RID_F64 */
+  int32_t b_dtype;           /* RID_F64, or RID_F32: then only MIXED-precision solves (FP32 outer
+                                products) are possible and no FP32 copy is made */
   const void* bris_ia_dev;   /* (naux_ris, no, nv) or NULL */
   const void* bris_ij_dev;
   const void* bris_ab_dev;
-  int32_t bris_dtype;        /* RID_F64 */
+  int32_t bris_dtype;        /* RID_F64, or RID_F32: then the ris model runs in BF16 only */
 } rid_problem_desc;
 
 typedef struct {
@@ -241,7 +242,11 @@ RID_API rid_status rid_profile_read(rid_context* ctx, rid_kernel_stat* out, int3
 /* ---- batched solves (many molecules per launch) -------------------------
  * A request is an eigen-solve (kind 0: k, mode) or a polarizability solve
  * (kind 1: nrhs, p_dev, nfreq, omega_host).  Results are written into the
- * caller-owned rid_result of each request. */
+ * caller-owned rid_result of each request.  rid_batch_solve runs up to 16
+ * solves at once, each on a stream of its own; the operator products of all
+ * solves waiting at the same time go out together, one persistent grouped
+ * GEMM launch per contraction stage and tile shape.  Each result equals
+ * that of the same request solved alone.  Returns the worst status. */
 typedef struct {
   int32_t kind;            /* 0 = eigen, 1 = polarizability */
   int32_t k, mode;         /* eigen */
@@ -263,10 +268,18 @@ typedef struct {
 RID_API rid_status rid_batch_solve(rid_context* ctx, int32_t n, rid_problem* const* probs,
                            const rid_request* reqs, rid_result* results);
 
+/* Estimated device bytes a request needs beyond its problem's borrowed
+ * tensors (subspace, products, inner-solve blocks, scratch, FP32 copies of
+ * FP64 tensors for a mixed-precision solve); the server admits by it. */
+RID_API rid_status rid_request_footprint(const rid_problem* prob, const rid_request* req, uint64_t* bytes);
+
 /* ---- continuous-batching server -----------------------------------------
- * Requests are admitted while their device footprint fits hbm_budget_bytes
- * and a slot is free; every engine tick advances every running request by one
- * outer iteration.  States: queued -> running -> done / failed / cancelled. */
+ * Requests are admitted in arrival order while their estimated device
+ * footprint fits hbm_budget_bytes and one of max_slots (1..64) slots is free.
+ * Admitted requests run at the same time, each keeping its subspace in device
+ * memory; their operator products are grouped as in rid_batch_solve, and a
+ * request admitted while others run joins their grouped launches at once.
+ * States: queued -> running -> done / failed / cancelled. */
 typedef struct {
   uint64_t hbm_budget_bytes;
   int32_t max_slots;

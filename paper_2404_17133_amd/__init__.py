@@ -5,6 +5,7 @@ include/rid.h); this package is its thin Python binding.  Importing it loads
 the library and fails when it is not built.
 """
 
+from . import _binding as binding  # noqa: F401  (status codes and structs)
 from ._binding import LIB_PATH, lib  # noqa: F401  (raises ImportError if the library is missing)
 from .solver import (  # noqa: F401
     Context,
@@ -14,4 +15,6 @@ from .solver import (  # noqa: F401
     batch_solve,
     default_opts,
     make_request,
+    make_result,
+    request_footprint,
 )

@@ -131,6 +131,7 @@ PROTOTYPES = {
     "rid_problem_create": (I32, [P, ctypes.POINTER(rid_problem_desc), PP]),
     "rid_problem_destroy": (I32, [P]),
     "rid_problem_footprint": (I32, [P, ctypes.POINTER(ctypes.c_uint64)]),
+    "rid_request_footprint": (I32, [P, ctypes.POINTER(rid_request), ctypes.POINTER(ctypes.c_uint64)]),
     "rid_problem_window": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "rid_solve_opts_default": (None, [ctypes.POINTER(rid_solve_opts)]),
     "rid_apply_operator": (I32, [P, I32, I32, I32, P, P, P]),

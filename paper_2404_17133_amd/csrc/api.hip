@@ -147,11 +147,12 @@ rid_status rid_problem_create(rid_context* ctx, const rid_problem_desc* d, rid_p
     RID_CHECK((long)d->no * d->nv <= (1L << 28), RID_ERR_SHAPE, "no*nv too large");
     RID_CHECK(d->naux_ris >= 0 && d->naux_ris_k >= 0 && d->naux_ris_k <= d->naux_ris, RID_ERR_SHAPE,
               "need 0 <= naux_ris_k <= naux_ris");
-    RID_CHECK(d->b_dtype == RID_F64, RID_ERR_DTYPE, "tensors must be FP64");
+    RID_CHECK(d->b_dtype == RID_F64 || d->b_dtype == RID_F32, RID_ERR_DTYPE, "tensors must be FP64 or FP32");
     RID_CHECK(d->eps_occ_host && d->eps_vir_host && d->b_ia_dev && d->b_ij_dev && d->b_ab_dev, RID_ERR_INVALID_ARG,
               "null tensor or energy pointer");
     if (d->naux_ris > 0) {
-      RID_CHECK(d->bris_dtype == RID_F64, RID_ERR_DTYPE, "ris tensors must be FP64");
+      RID_CHECK(d->bris_dtype == RID_F64 || d->bris_dtype == RID_F32, RID_ERR_DTYPE,
+                "ris tensors must be FP64 or FP32");
       RID_CHECK(d->bris_ia_dev && d->bris_ij_dev && d->bris_ab_dev, RID_ERR_INVALID_ARG, "null ris tensor pointer");
     }
     RID_CHECK(std::isfinite(d->a_x), RID_ERR_INVALID_ARG, "a_x must be finite");
@@ -173,13 +174,27 @@ rid_status rid_problem_create(rid_context* ctx, const rid_problem_desc* d, rid_p
       P->t_cut = d->t_cut_ha;
       P->eps_occ.assign(d->eps_occ_host, d->eps_occ_host + d->no);
       P->eps_vir.assign(d->eps_vir_host, d->eps_vir_host + d->nv);
-      P->b_ia = static_cast<const double*>(d->b_ia_dev);
-      P->b_ij = static_cast<const double*>(d->b_ij_dev);
-      P->b_ab = static_cast<const double*>(d->b_ab_dev);
+      P->b_dt = d->b_dtype;
+      if (d->b_dtype == RID_F64) {
+        P->b_ia = static_cast<const double*>(d->b_ia_dev);
+        P->b_ij = static_cast<const double*>(d->b_ij_dev);
+        P->b_ab = static_cast<const double*>(d->b_ab_dev);
+      } else {
+        P->b_ia_f = static_cast<const float*>(d->b_ia_dev);
+        P->b_ij_f = static_cast<const float*>(d->b_ij_dev);
+        P->b_ab_f = static_cast<const float*>(d->b_ab_dev);
+      }
       if (d->naux_ris > 0) {
-        P->bris_ia = static_cast<const double*>(d->bris_ia_dev);
-        P->bris_ij = static_cast<const double*>(d->bris_ij_dev);
-        P->bris_ab = static_cast<const double*>(d->bris_ab_dev);
+        P->bris_dt = d->bris_dtype;
+        if (d->bris_dtype == RID_F64) {
+          P->bris_ia = static_cast<const double*>(d->bris_ia_dev);
+          P->bris_ij = static_cast<const double*>(d->bris_ij_dev);
+          P->bris_ab = static_cast<const double*>(d->bris_ab_dev);
+        } else {
+          P->bris_ia_f = static_cast<const float*>(d->bris_ia_dev);
+          P->bris_ij_f = static_cast<const float*>(d->bris_ij_dev);
+          P->bris_ab_f = static_cast<const float*>(d->bris_ab_dev);
+        }
       }
       // exchange window of the ris model (energies sorted)
       const double homo = P->eps_occ.back(), lumo = P->eps_vir.front();
@@ -340,6 +355,13 @@ rid_status rid_batch_solve(rid_context* ctx, int32_t n, rid_problem* const* prob
     use_device(ctx);
     return rid::batch_run(ctx, n, probs, reqs, results);
   });
+}
+
+rid_status rid_request_footprint(const rid_problem* prob, const rid_request* req, uint64_t* bytes) {
+  if (!prob || !req || !bytes) return RID_ERR_INVALID_ARG;
+  if (req->kind != 0 && req->kind != 1) return RID_ERR_INVALID_ARG;
+  *bytes = rid::request_footprint(prob, *req);
+  return RID_OK;
 }
 
 rid_status rid_server_create(rid_context* ctx, const rid_server_opts* opts, rid_server** out) {

@@ -70,22 +70,25 @@ Profiler::~Profiler() {
   for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
-ProfScope::ProfScope(rid_context* c, const char* name, double fl, double by) : ctx(c), flops(fl), bytes(by) {
+ProfScope::ProfScope(rid_context* c, hipStream_t s, const char* name, double fl, double by)
+    : ctx(c), st(s), flops(fl), bytes(by) {
   if (!ctx || !ctx->prof.on) return;
+  std::lock_guard<std::mutex> g(ctx->prof.mu);
   fam = ctx->prof.family(name);
   a = ctx->prof.get_event();
-  RID_HIP(hipEventRecord(a, ctx->stream));
+  RID_HIP(hipEventRecord(a, st));
 }
 
 ProfScope::~ProfScope() {
   if (fam < 0) return;
+  std::lock_guard<std::mutex> g(ctx->prof.mu);
   hipEvent_t b = nullptr;
   try {
     b = ctx->prof.get_event();
   } catch (...) {
     return;
   }
-  (void)hipEventRecord(b, ctx->stream);
+  (void)hipEventRecord(b, st);
   ctx->prof.recs.push_back(Profiler::Rec{fam, a, b, flops, bytes});
 }
 
@@ -118,12 +121,49 @@ void dev_free(rid_context* ctx, void* p) {
 
 void DevBuf::release() {
   if (p && ctx) {
-    // memory may still be in use by queued work on the context stream
-    (void)hipStreamSynchronize(ctx->stream);
-    dev_free(ctx, p);
+    bool park = false;
+    {
+      std::lock_guard<std::mutex> g(ctx->grave_mu);
+      if (ctx->defer_free > 0) {
+        ctx->graveyard.push_back(p);
+        ctx->grave_bytes += bytes;
+        park = true;
+      }
+    }
+    if (!park) {
+      // memory may still be in use by queued work on the context stream
+      (void)hipStreamSynchronize(ctx->stream);
+      dev_free(ctx, p);
+    }
   }
   p = nullptr;
   bytes = 0;
+}
+
+void flush_graveyard(rid_context* ctx) {
+  std::vector<void*> v;
+  {
+    std::lock_guard<std::mutex> g(ctx->grave_mu);
+    v.swap(ctx->graveyard);
+    ctx->grave_bytes = 0;
+  }
+  if (v.empty()) return;
+  (void)hipDeviceSynchronize();
+  for (void* q : v) dev_free(ctx, q);
+}
+
+DeferFree::DeferFree(rid_context* c) : ctx(c) {
+  std::lock_guard<std::mutex> g(ctx->grave_mu);
+  ctx->defer_free += 1;
+}
+
+DeferFree::~DeferFree() {
+  bool last;
+  {
+    std::lock_guard<std::mutex> g(ctx->grave_mu);
+    last = --ctx->defer_free == 0;
+  }
+  if (last) flush_graveyard(ctx);
 }
 
 void DevBuf::ensure(size_t n) {
@@ -138,8 +178,11 @@ void check_operator(const rid_problem* P, int kind, int prec) {
   RID_CHECK(kind >= OPK_A && kind <= OPK_TPAIR, RID_ERR_INVALID_ARG, "unknown operator");
   RID_CHECK(prec >= PREC_F64 && prec <= PREC_BF16, RID_ERR_INVALID_ARG, "unknown precision");
   const bool ris = kind == OPK_T || kind == OPK_TPAIR;
-  if (ris) RID_CHECK(P->naux_ris > 0 && P->bris_ia, RID_ERR_INVALID_ARG, "problem has no ris tensor");
+  if (ris) RID_CHECK(P->has_ris(), RID_ERR_INVALID_ARG, "problem has no ris tensor");
   if (!ris) RID_CHECK(prec != PREC_BF16, RID_ERR_DTYPE, "BF16 is only offered for the ris operators");
+  if (prec == PREC_F64)
+    RID_CHECK((ris ? P->bris_dt : P->b_dt) == RID_F64, RID_ERR_DTYPE,
+              "an FP64 product needs FP64 tensors (the problem was created with FP32 ones)");
 }
 
 namespace {
@@ -227,13 +270,17 @@ bool autotune_enabled() {
 // `launch` must be idempotent (GEMM_STORE or GEMM_PARTIAL_SET), so the
 // candidate runs leave the same result as a single run of the winner.
 template <typename E, typename F>
-GemmChoice tuned(rid_context* ctx, int family, long M, long N, int nz, int np, int K, bool reduction, F&& launch) {
+GemmChoice tuned(rid_context* ctx, int family, long M, long N, int nz, int np, int K, bool reduction, hipStream_t st,
+                 F&& launch) {
   const TuneKey key{family, (int)sizeof(E), M, N, nz, np, K};
-  auto it = ctx->tune.find(key);
-  if (it != ctx->tune.end()) {
-    const GemmChoice ch{it->second.cfg, it->second.nsub, it->second.pps};
-    launch(ch);
-    return ch;
+  {
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end()) {
+      const GemmChoice ch{it->second.cfg, it->second.nsub, it->second.pps};
+      launch(ch);
+      return ch;
+    }
   }
   GemmChoice best = plan_for<E>(0, M, N, nz, np, K, reduction);
   if (!autotune_enabled()) {
@@ -251,9 +298,9 @@ GemmChoice tuned(rid_context* ctx, int family, long M, long N, int nz, int np, i
     for (int cfg = 0; cfg < 3; ++cfg) {
       const GemmChoice ch = plan_for<E>(cfg, M, N, nz, np, K, reduction);
       launch(ch);  // warm
-      RID_HIP(hipEventRecord(a, ctx->stream));
+      RID_HIP(hipEventRecord(a, st));
       launch(ch);
-      RID_HIP(hipEventRecord(b, ctx->stream));
+      RID_HIP(hipEventRecord(b, st));
       RID_HIP(hipEventSynchronize(b));
       float ms = 0.0f;
       RID_HIP(hipEventElapsedTime(&ms, a, b));
@@ -267,299 +314,570 @@ GemmChoice tuned(rid_context* ctx, int family, long M, long N, int nz, int np, i
     (void)hipEventDestroy(b);
     if (last.cfg != best.cfg) launch(best);
   }
-  ctx->tune[key] = TuneVal{best.cfg, best.nsub, best.pps};
+  {
+    std::lock_guard<std::mutex> g(ctx->tune_mu);
+    ctx->tune[key] = TuneVal{best.cfg, best.nsub, best.pps};
+  }
   return best;
 }
 
-template <typename E>
-void run_operator(rid_problem* P, const OpView<E>& ov, bool pair, int nvec, const double* x, double* y,
-                  double* y2) {
-  typedef typename GemmTag<E>::type G;
-  typedef typename AccOf<E>::type Acc;
-  hipStream_t st = P->ctx->stream;
-  rid_context* ctx = P->ctx;
-  const std::string pre = ov.ris ? "ris_" : "";
-  const double esz = (double)sizeof(E), asz = (double)sizeof(Acc);
-  OpWork& w = P->work;
-  const int no = P->no, nv = P->nv;
-  const long n = P->n();
-  const int no_a = ov.no_a, nv_a = ov.nv_a, i0 = ov.i0;
-  const bool exch = P->a_x != 0.0 && ov.naux_k > 0 && no_a > 0 && nv_a > 0;
-
-  // 1. vector layouts in the compute type
-  w.xc.ensure(sizeof(E) * nvec * n);
-  if (exch) {
-    w.xa.ensure(sizeof(E) * (size_t)nvec * no_a * nv_a);
-    w.xt.ensure(sizeof(E) * (size_t)nvec * no_a * nv_a);
-  }
-  prep_x<E>(x, nvec, no, nv, i0, no_a, nv_a, w.xc.as<E>(), exch ? w.xa.as<E>() : nullptr,
-            exch ? w.xt.as<E>() : nullptr, st);
-
-  // 2. Coulomb forward: t[v][P] = sum_i sum_a Xc[v][i nv + a] B[P][i nv + a]
-  const int naux_j = ov.naux_j;
-  double* t64 = nullptr;
-  if (naux_j > 0) {
-    // partial buffer sized for the largest split count any plan can pick
-    w.tpart.ensure(sizeof(Acc) * (size_t)std::min(no, 64) * nvec * naux_j);
-    w.t64.ensure(sizeof(double) * (size_t)nvec * naux_j);
-    GemmParams g{};
-    g.A = w.xc.p;
-    g.B = ov.b_ia;
-    g.C = w.tpart.p;
-    g.M = nvec;
-    g.N = naux_j;
-    g.K = nv;
-    g.np = no;
-    g.nz2 = 1;
-    g.lda = n;
-    g.ldb = n;
-    g.ldc = naux_j;
-    g.sAp = nv;
-    g.sBp = nv;
-    g.sCs = (long)nvec * naux_j;
-    g.alpha = 1.0;
-    g.mode = GEMM_PARTIAL_SET;
-    GemmChoice ch;
-    {
-      ProfScope ps(ctx, (pre + "coul_fwd").c_str(), 2.0 * nvec * naux_j * (double)n,
-                   esz * ((double)naux_j * n + (double)nvec * n));
-      ch = tuned<E>(ctx, GF_COUL, nvec, naux_j, 1, no, nv, true, [&](const GemmChoice& c) {
-        g.pps = c.pps;
-        gemm_nt<G>(g, 1, c.nsub, st, c.cfg, GF_COUL);
-      });
-    }
-    const int nsplit = ch.nsub;
-    reduce_splits<Acc>(w.tpart.as<Acc>(), nsplit, (long)nvec * naux_j, (long)nvec * naux_j, w.t64.as<double>(), st);
-    t64 = w.t64.as<double>();
-    w.jbuf.ensure(sizeof(double) * nvec * n);
-    {
-      ProfScope ps(ctx, (pre + "coul_bwd").c_str(), 2.0 * nvec * naux_j * (double)n,
-                   esz * (double)naux_j * n * ceil_div(nvec, 8) + 8.0 * nvec * n);
-      coul_bwd<E>(t64, ov.b_ia, naux_j, n, nvec, w.jbuf.as<double>(), st);
-    }
-  }
-
-  // 3. exchange products, chunked over the auxiliary index
-  int ns_w = 0, ns_wp = 0;
-  const long rows = (long)no_a * nvec;  // output rows (i, v)
-  const long part_elems = rows * nv_a;
-  if (exch) {
-    const int nk = ov.naux_k;
-    const long s_per_p = (long)no_a * nvec * nv_a;
-    const long q_per_p = (long)no_a * nvec * no_a;
-    const long per_p = std::max(s_per_p, pair ? q_per_p : 0L);
-    const long target = 256L << 20;  // bytes of intermediate per chunk
-    const int pc = (int)std::max<long>(1, std::min<long>(nk, target / std::max<long>(1, per_p * (long)sizeof(E))));
-    int max_splits = 1;
-    for (int cfg = 0; cfg < 3; ++cfg) {
-      max_splits = std::max(max_splits, plan_for<E>(cfg, rows, nv_a, 1, pc, nv_a, true).nsub);
-      max_splits = std::max(max_splits, plan_for<E>(cfg, rows, nv_a, 1, pc, no_a, true).nsub);
-    }
-    w.s.ensure(sizeof(E) * (size_t)pc * s_per_p);
-    w.wpart.ensure(sizeof(Acc) * (size_t)max_splits * part_elems);
-    if (pair) {
-      w.q.ensure(sizeof(E) * (size_t)pc * q_per_p);
-      w.wppart.ensure(sizeof(Acc) * (size_t)max_splits * part_elems);
-    }
-    GemmChoice cw{}, cwp{};
-    for (int c0 = 0; c0 < nk; c0 += pc) {
-      const int pcc = std::min(pc, nk - c0);
-      const bool first = c0 == 0;
-      {  // S^P = B^P_ij (window) x Xt
-        GemmParams g{};
-        g.A = ov.b_ij + (long)c0 * no * no + (long)i0 * no + i0;
-        g.B = w.xt.p;
-        g.C = w.s.p;
-        g.M = no_a;
-        g.N = nvec * nv_a;
-        g.K = no_a;
-        g.np = 1;
-        g.pps = 1;
-        g.nz2 = 1;
-        g.lda = no;
-        g.ldb = no_a;
-        g.ldc = (long)nvec * nv_a;
-        g.sA1 = (long)no * no;
-        g.sC1 = s_per_p;
-        g.alpha = 1.0;
-        g.mode = GEMM_STORE;
-        ProfScope ps(ctx, (pre + "exch_s").c_str(), 2.0 * no_a * (double)nvec * nv_a * no_a * pcc,
-                     esz * ((double)pcc * no_a * no_a + (double)nvec * nv_a * no_a + (double)pcc * s_per_p));
-        tuned<E>(ctx, GF_EXCH_S, no_a, (long)nvec * nv_a, pcc, 1, no_a, false, [&](const GemmChoice& ch) {
-          gemm_nt<G>(g, pcc, 1, st, ch.cfg, GF_EXCH_S);
-        });
-      }
-      {  // W += sum_P S^P B^P_ab (window)
-        GemmParams g{};
-        g.A = w.s.p;
-        g.B = ov.b_ab + (long)c0 * nv * nv;
-        g.C = w.wpart.p;
-        g.M = (int)rows;
-        g.N = nv_a;
-        g.K = nv_a;
-        g.np = pcc;
-        g.nz2 = 1;
-        g.lda = nv_a;
-        g.ldb = nv;
-        g.ldc = nv_a;
-        g.sAp = s_per_p;
-        g.sBp = (long)nv * nv;
-        g.sCs = part_elems;
-        g.alpha = 1.0;
-        g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
-        ProfScope ps(ctx, (pre + "exch_w").c_str(), 2.0 * rows * (double)nv_a * nv_a * pcc,
-                     esz * ((double)pcc * s_per_p + (double)pcc * nv_a * nv_a) +
-                         asz * part_elems * (first ? 1.0 : 2.0));
-        auto launch = [&](const GemmChoice& ch) {
-          g.pps = ch.pps;
-          gemm_nt<G>(g, 1, ch.nsub, st, ch.cfg, GF_EXCH_W);
-        };
-        if (first)
-          cw = tuned<E>(ctx, GF_EXCH_W, rows, nv_a, 1, pcc, nv_a, true, launch);
-        else
-          launch(cw);
-      }
-      if (pair) {
-        {  // Q^P = B^P_ia (window) x Xa^T
-          GemmParams g{};
-          g.A = ov.b_ia + (long)c0 * n + (long)i0 * nv;
-          g.B = w.xa.p;
-          g.C = w.q.p;
-          g.M = no_a;
-          g.N = nvec * no_a;
-          g.K = nv_a;
-          g.np = 1;
-          g.pps = 1;
-          g.nz2 = 1;
-          g.lda = nv;
-          g.ldb = nv_a;
-          g.ldc = (long)nvec * no_a;
-          g.sA1 = n;
-          g.sC1 = q_per_p;
-          g.alpha = 1.0;
-          g.mode = GEMM_STORE;
-          ProfScope ps(ctx, (pre + "exch_q").c_str(), 2.0 * no_a * (double)nvec * no_a * nv_a * pcc,
-                       esz * ((double)pcc * no_a * nv_a + (double)nvec * no_a * nv_a + (double)pcc * q_per_p));
-          tuned<E>(ctx, GF_EXCH_Q, no_a, (long)nvec * no_a, pcc, 1, nv_a, false, [&](const GemmChoice& ch) {
-            gemm_nt<G>(g, pcc, 1, st, ch.cfg, GF_EXCH_Q);
-          });
-        }
-        {  // W' += sum_P Q^P B^P_ja (window), B_ja read from the transposed copy
-          GemmParams g{};
-          g.A = w.q.p;
-          g.B = ov.b_ai + (long)c0 * nv * no + i0;
-          g.C = w.wppart.p;
-          g.M = (int)rows;
-          g.N = nv_a;
-          g.K = no_a;
-          g.np = pcc;
-          g.nz2 = 1;
-          g.lda = no_a;
-          g.ldb = no;
-          g.ldc = nv_a;
-          g.sAp = q_per_p;
-          g.sBp = (long)nv * no;
-          g.sCs = part_elems;
-          g.alpha = 1.0;
-          g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
-          ProfScope ps(ctx, (pre + "exch_wp").c_str(), 2.0 * rows * (double)nv_a * no_a * pcc,
-                       esz * ((double)pcc * q_per_p + (double)pcc * nv_a * no_a) +
-                           asz * part_elems * (first ? 1.0 : 2.0));
-          auto launch = [&](const GemmChoice& ch) {
-            g.pps = ch.pps;
-            gemm_nt<G>(g, 1, ch.nsub, st, ch.cfg, GF_EXCH_WP);
-          };
-          if (first)
-            cwp = tuned<E>(ctx, GF_EXCH_WP, rows, nv_a, 1, pcc, no_a, true, launch);
-          else
-            launch(cwp);
-        }
-      }
-    }
-    ns_w = cw.nsub;
-    ns_wp = pair ? cwp.nsub : 0;
-  }
-
-  // 4. combine in f64
-  CombineArgs c{};
-  c.x = x;
-  c.de = P->de.as<double>();
-  c.j = naux_j > 0 ? w.jbuf.as<double>() : nullptr;
-  c.y = y;
-  c.y2 = y2;
-  c.nvec = nvec;
-  c.no = no;
-  c.nv = nv;
-  c.i0 = i0;
-  c.no_a = no_a;
-  c.nv_a = nv_a;
-  c.ns_w = ns_w;
-  c.ns_wp = ns_wp;
-  c.sstride = part_elems;
-  c.cj = pair ? 4.0 : 2.0;
-  c.a_x = P->a_x;
-  c.pair = pair ? 1 : 0;
-  ProfScope ps(ctx, (pre + "combine").c_str(), 0.0,
-               8.0 * nvec * n * (pair ? 5.0 : 3.0) + asz * (ns_w + ns_wp) * part_elems);
-  combine<Acc>(c, exch ? w.wpart.as<Acc>() : nullptr, (exch && pair) ? w.wppart.as<Acc>() : nullptr, st);
+// Lookup of a tuned launch shape (false when it has not been seen).
+bool tuned_lookup(rid_context* ctx, const TuneKey& key, GemmChoice* ch) {
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  auto it = ctx->tune.find(key);
+  if (it == ctx->tune.end()) return false;
+  *ch = GemmChoice{it->second.cfg, it->second.nsub, it->second.pps};
+  return true;
 }
 
 }  // namespace
 
+// Staging of grouped-GEMM descriptors: slots of pinned host memory and of
+// device memory.  A slot is reused once the copy that read it has run.
+struct DescRing {
+  static constexpr int kSlots = 32, kMembers = 128;
+  std::mutex mu;
+  DevBuf dev;
+  void* host = nullptr;
+  size_t slot_bytes = 0;
+  hipEvent_t ev[kSlots] = {};
+  int next = 0;
+  explicit DescRing(rid_context* c) : dev(c) {
+    slot_bytes = (gemm_group_desc_bytes(kMembers) + 255) & ~(size_t)255;
+    dev.ensure(slot_bytes * kSlots);
+    RID_HIP(hipHostMalloc(&host, slot_bytes * kSlots, hipHostMallocDefault));
+    for (hipEvent_t& e : ev) RID_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  ~DescRing() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventSynchronize(e);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (host) (void)hipHostFree(host);
+  }
+};
+
+namespace {
+
+std::mutex g_ring_mu;
+
+// Launch the members of one stage that share a tile configuration: a plain
+// launch for one member, grouped persistent launches otherwise.
+template <typename G>
+void launch_members(rid_context* ctx, const std::vector<GemmGroup>& mem, int cfg, int family, hipStream_t st,
+                    int grid_cap) {
+  if (mem.empty()) return;
+  if (mem.size() == 1) {
+    gemm_nt<G>(mem[0].p, mem[0].nz, mem[0].nsplit, st, cfg, family);
+    return;
+  }
+  {
+    std::lock_guard<std::mutex> g(g_ring_mu);
+    if (!ctx->ring) ctx->ring = new DescRing(ctx);
+  }
+  DescRing& R = *ctx->ring;
+  std::lock_guard<std::mutex> g(R.mu);
+  for (size_t b = 0; b < mem.size(); b += DescRing::kMembers) {
+    const int n = (int)std::min<size_t>(DescRing::kMembers, mem.size() - b);
+    const int slot = R.next;
+    R.next = (R.next + 1) % DescRing::kSlots;
+    RID_HIP(hipEventSynchronize(R.ev[slot]));
+    void* h = static_cast<char*>(R.host) + slot * R.slot_bytes;
+    void* d = static_cast<char*>(R.dev.p) + slot * R.slot_bytes;
+    gemm_grouped<G>(&mem[b], n, cfg, family, d, h, st, grid_cap);
+    RID_HIP(hipEventRecord(R.ev[slot], st));
+  }
+}
+
+// Members of one GEMM stage, by tile configuration.
+template <typename E>
+struct Stage {
+  typedef typename GemmTag<E>::type G;
+  std::vector<GemmGroup> mem[3];
+  void add(const GemmParams& p, int nz, const GemmChoice& ch) {
+    GemmParams q = p;
+    q.pps = ch.pps;
+    mem[ch.cfg].push_back(GemmGroup{q, nz, ch.nsub});
+  }
+  void launch(rid_context* ctx, int family, hipStream_t st) {
+    for (int c = 0; c < 3; ++c) launch_members<G>(ctx, mem[c], c, family, st, gemm_slots<E>(c));
+  }
+};
+
+// Either queue p into the stage (shape already tuned) or tune it now, which
+// launches it alone.  Returns the choice.
+template <typename E>
+GemmChoice plan_or_tune(rid_context* ctx, Stage<E>& stage, int family, GemmParams p, long M, long N, int nz, int np,
+                        int K, bool reduction, hipStream_t st) {
+  typedef typename GemmTag<E>::type G;
+  const TuneKey key{family, (int)sizeof(E), M, N, nz, np, K};
+  GemmChoice ch;
+  if (tuned_lookup(ctx, key, &ch)) {
+    stage.add(p, nz, ch);
+    return ch;
+  }
+  return tuned<E>(ctx, family, M, N, nz, np, K, reduction, st, [&](const GemmChoice& c) {
+    p.pps = reduction ? c.pps : 1;
+    gemm_nt<G>(p, nz, c.nsub, st, c.cfg, family);
+  });
+}
+
+template <typename E>
+OpView<E> make_view(rid_problem* P, bool ris);
+
+void fill_window(rid_problem* P, bool ris, int& naux_j, int& naux_k, int& i0, int& no_a, int& nv_a) {
+  // the outer operator uses every row and the full orbital ranges
+  naux_j = ris ? P->naux_ris : P->naux;
+  naux_k = ris ? P->naux_ris_k : P->naux;
+  i0 = ris ? P->i0 : 0;
+  no_a = ris ? P->no - P->i0 : P->no;
+  nv_a = ris ? P->nv_act : P->nv;
+}
+
+template <>
+OpView<double> make_view<double>(rid_problem* P, bool ris) {
+  P->ensure_f64_aux();
+  OpView<double> ov;
+  ov.b_ia = ris ? P->bris_ia : P->b_ia;
+  ov.b_ij = ris ? P->bris_ij : P->b_ij;
+  ov.b_ab = ris ? P->bris_ab : P->b_ab;
+  ov.b_ai = ris ? P->bris_ai64.as<double>() : P->b_ai64.as<double>();
+  fill_window(P, ris, ov.naux_j, ov.naux_k, ov.i0, ov.no_a, ov.nv_a);
+  ov.ris = ris;
+  return ov;
+}
+
+template <>
+OpView<float> make_view<float>(rid_problem* P, bool ris) {
+  RID_CHECK(!ris, RID_ERR_DTYPE, "the ris operators run in FP64 or BF16");
+  P->ensure_f32();
+  OpView<float> ov;
+  ov.b_ia = P->ia32();
+  ov.b_ij = P->ij32();
+  ov.b_ab = P->ab32();
+  ov.b_ai = P->b_ai32.as<float>();
+  fill_window(P, ris, ov.naux_j, ov.naux_k, ov.i0, ov.no_a, ov.nv_a);
+  ov.ris = ris;
+  return ov;
+}
+
+template <>
+OpView<uint16_t> make_view<uint16_t>(rid_problem* P, bool ris) {
+  P->ensure_bf16();
+  OpView<uint16_t> ov;
+  ov.b_ia = P->bris_ia16.as<uint16_t>();
+  ov.b_ij = P->bris_ij16.as<uint16_t>();
+  ov.b_ab = P->bris_ab16.as<uint16_t>();
+  ov.b_ai = P->bris_ai16.as<uint16_t>();
+  fill_window(P, ris, ov.naux_j, ov.naux_k, ov.i0, ov.no_a, ov.nv_a);
+  ov.ris = ris;
+  return ov;
+}
+
+// Per-job quantities of one product.
+template <typename E>
+struct JobPlan {
+  OpJob* j = nullptr;
+  OpView<E> ov;
+  bool pair = false, exch = false;
+  int no = 0, nv = 0, no_a = 0, nv_a = 0, i0 = 0, naux_j = 0, nk = 0, pc = 1, nchunks = 0, nvec = 0;
+  long n = 0, rows = 0, part_elems = 0, s_per_p = 0, q_per_p = 0;
+  GemmChoice cw{}, cwp{};
+  int ns_coul = 1;
+};
+
+// Products of jobs that share element type E and operator (outer or ris).
+template <typename E>
+void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipStream_t st) {
+  typedef typename AccOf<E>::type Acc;
+  const std::string pre = ris ? "ris_" : "";
+  const double esz = (double)sizeof(E), asz = (double)sizeof(Acc);
+  std::vector<JobPlan<E>> pl(jobs.size());
+
+  // 1. plans and vector layouts in the compute type
+  {
+    ProfScope ps(ctx, st, (pre + "prep").c_str(), 0.0, 0.0);
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      JobPlan<E>& J = pl[q];
+      OpJob* j = jobs[q];
+      rid_problem* P = j->P;
+      J.j = j;
+      J.ov = make_view<E>(P, ris);
+      J.pair = j->kind == OPK_PAIR || j->kind == OPK_TPAIR;
+      J.no = P->no;
+      J.nv = P->nv;
+      J.n = P->n();
+      J.nvec = j->nvec;
+      J.no_a = J.ov.no_a;
+      J.nv_a = J.ov.nv_a;
+      J.i0 = J.ov.i0;
+      J.naux_j = J.ov.naux_j;
+      J.exch = P->a_x != 0.0 && J.ov.naux_k > 0 && J.no_a > 0 && J.nv_a > 0;
+      OpWork& w = *j->work;
+      w.xc.ensure(sizeof(E) * J.nvec * J.n);
+      if (J.exch) {
+        w.xa.ensure(sizeof(E) * (size_t)J.nvec * J.no_a * J.nv_a);
+        w.xt.ensure(sizeof(E) * (size_t)J.nvec * J.no_a * J.nv_a);
+      }
+      prep_x<E>(j->x, J.nvec, J.no, J.nv, J.i0, J.no_a, J.nv_a, w.xc.as<E>(), J.exch ? w.xa.as<E>() : nullptr,
+                J.exch ? w.xt.as<E>() : nullptr, st);
+      J.rows = (long)J.no_a * J.nvec;  // exchange output rows (i, v)
+      J.part_elems = J.rows * J.nv_a;
+      if (J.exch) {
+        J.nk = J.ov.naux_k;
+        J.s_per_p = (long)J.no_a * J.nvec * J.nv_a;
+        J.q_per_p = (long)J.no_a * J.nvec * J.no_a;
+        const long per_p = std::max(J.s_per_p, J.pair ? J.q_per_p : 0L);
+        const long target = 256L << 20;  // bytes of intermediate per chunk of the auxiliary index
+        J.pc = (int)std::max<long>(1, std::min<long>(J.nk, target / std::max<long>(1, per_p * (long)sizeof(E))));
+        J.nchunks = ceil_div(J.nk, J.pc);
+        int max_splits = 1;
+        for (int cfg = 0; cfg < 3; ++cfg) {
+          max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.nv_a, true).nsub);
+          max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.no_a, true).nsub);
+        }
+        w.s.ensure(sizeof(E) * (size_t)J.pc * J.s_per_p);
+        w.wpart.ensure(sizeof(Acc) * (size_t)max_splits * J.part_elems);
+        if (J.pair) {
+          w.q.ensure(sizeof(E) * (size_t)J.pc * J.q_per_p);
+          w.wppart.ensure(sizeof(Acc) * (size_t)max_splits * J.part_elems);
+        }
+      }
+    }
+  }
+
+  // 2. Coulomb forward: t[v][P] = sum_i sum_a Xc[v][i nv + a] B[P][i nv + a]
+  {
+    Stage<E> stage;
+    ProfScope ps(ctx, st, (pre + "coul_fwd").c_str(), 0.0, 0.0);
+    for (JobPlan<E>& J : pl) {
+      if (J.naux_j <= 0) continue;
+      OpWork& w = *J.j->work;
+      // partial buffer sized for the largest split count any plan can pick
+      w.tpart.ensure(sizeof(Acc) * (size_t)std::min(J.no, 64) * J.nvec * J.naux_j);
+      w.t64.ensure(sizeof(double) * (size_t)J.nvec * J.naux_j);
+      GemmParams g{};
+      g.A = w.xc.p;
+      g.B = J.ov.b_ia;
+      g.C = w.tpart.p;
+      g.M = J.nvec;
+      g.N = J.naux_j;
+      g.K = J.nv;
+      g.np = J.no;
+      g.pps = 1;
+      g.nz2 = 1;
+      g.lda = J.n;
+      g.ldb = J.n;
+      g.ldc = J.naux_j;
+      g.sAp = J.nv;
+      g.sBp = J.nv;
+      g.sCs = (long)J.nvec * J.naux_j;
+      g.alpha = 1.0;
+      g.mode = GEMM_PARTIAL_SET;
+      ps.flops += 2.0 * J.nvec * J.naux_j * (double)J.n;
+      ps.bytes += esz * ((double)J.naux_j * J.n + (double)J.nvec * J.n);
+      J.ns_coul = plan_or_tune<E>(ctx, stage, GF_COUL, g, J.nvec, J.naux_j, 1, J.no, J.nv, true, st).nsub;
+    }
+    stage.launch(ctx, GF_COUL, st);
+  }
+  {
+    ProfScope ps(ctx, st, (pre + "coul_bwd").c_str(), 0.0, 0.0);
+    for (JobPlan<E>& J : pl) {
+      if (J.naux_j <= 0) continue;
+      OpWork& w = *J.j->work;
+      reduce_splits<Acc>(w.tpart.as<Acc>(), J.ns_coul, (long)J.nvec * J.naux_j, (long)J.nvec * J.naux_j,
+                         w.t64.as<double>(), st);
+      w.jbuf.ensure(sizeof(double) * J.nvec * J.n);
+      coul_bwd<E>(w.t64.as<double>(), J.ov.b_ia, J.naux_j, J.n, J.nvec, w.jbuf.as<double>(), st);
+      ps.flops += 2.0 * J.nvec * J.naux_j * (double)J.n;
+      ps.bytes += esz * (double)J.naux_j * J.n * ceil_div(J.nvec, 8) + 8.0 * J.nvec * J.n;
+    }
+  }
+
+  // 3. exchange products, chunked over the auxiliary index; chunk c of every
+  // job goes out in the same grouped launches
+  int max_chunks = 0;
+  bool any_pair = false;
+  for (const JobPlan<E>& J : pl) {
+    if (!J.exch) continue;
+    max_chunks = std::max(max_chunks, J.nchunks);
+    any_pair = any_pair || J.pair;
+  }
+  for (int c = 0; c < max_chunks; ++c) {
+    {  // S^P = B^P_ij (window) x Xt
+      Stage<E> stage;
+      ProfScope ps(ctx, st, (pre + "exch_s").c_str(), 0.0, 0.0);
+      for (JobPlan<E>& J : pl) {
+        if (!J.exch || c >= J.nchunks) continue;
+        const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
+        OpWork& w = *J.j->work;
+        GemmParams g{};
+        g.A = J.ov.b_ij + (long)c0 * J.no * J.no + (long)J.i0 * J.no + J.i0;
+        g.B = w.xt.p;
+        g.C = w.s.p;
+        g.M = J.no_a;
+        g.N = J.nvec * J.nv_a;
+        g.K = J.no_a;
+        g.np = 1;
+        g.pps = 1;
+        g.nz2 = 1;
+        g.lda = J.no;
+        g.ldb = J.no_a;
+        g.ldc = (long)J.nvec * J.nv_a;
+        g.sA1 = (long)J.no * J.no;
+        g.sC1 = J.s_per_p;
+        g.alpha = 1.0;
+        g.mode = GEMM_STORE;
+        ps.flops += 2.0 * J.no_a * (double)J.nvec * J.nv_a * J.no_a * pcc;
+        ps.bytes += esz * ((double)pcc * J.no_a * J.no_a + (double)J.nvec * J.nv_a * J.no_a + (double)pcc * J.s_per_p);
+        plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.nv_a, pcc, 1, J.no_a, false, st);
+      }
+      stage.launch(ctx, GF_EXCH_S, st);
+    }
+    {  // W += sum_P S^P B^P_ab (window)
+      Stage<E> stage;
+      ProfScope ps(ctx, st, (pre + "exch_w").c_str(), 0.0, 0.0);
+      for (JobPlan<E>& J : pl) {
+        if (!J.exch || c >= J.nchunks) continue;
+        const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
+        const bool first = c == 0;
+        OpWork& w = *J.j->work;
+        GemmParams g{};
+        g.A = w.s.p;
+        g.B = J.ov.b_ab + (long)c0 * J.nv * J.nv;
+        g.C = w.wpart.p;
+        g.M = (int)J.rows;
+        g.N = J.nv_a;
+        g.K = J.nv_a;
+        g.np = pcc;
+        g.pps = 1;
+        g.nz2 = 1;
+        g.lda = J.nv_a;
+        g.ldb = J.nv;
+        g.ldc = J.nv_a;
+        g.sAp = J.s_per_p;
+        g.sBp = (long)J.nv * J.nv;
+        g.sCs = J.part_elems;
+        g.alpha = 1.0;
+        g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
+        ps.flops += 2.0 * J.rows * (double)J.nv_a * J.nv_a * pcc;
+        ps.bytes += esz * ((double)pcc * J.s_per_p + (double)pcc * J.nv_a * J.nv_a) +
+                    asz * J.part_elems * (first ? 1.0 : 2.0);
+        if (first)
+          J.cw = plan_or_tune<E>(ctx, stage, GF_EXCH_W, g, J.rows, J.nv_a, 1, pcc, J.nv_a, true, st);
+        else
+          stage.add(g, 1, J.cw);
+      }
+      stage.launch(ctx, GF_EXCH_W, st);
+    }
+    if (!any_pair) continue;
+    {  // Q^P = B^P_ia (window) x Xa^T
+      Stage<E> stage;
+      ProfScope ps(ctx, st, (pre + "exch_q").c_str(), 0.0, 0.0);
+      for (JobPlan<E>& J : pl) {
+        if (!J.exch || !J.pair || c >= J.nchunks) continue;
+        const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
+        OpWork& w = *J.j->work;
+        GemmParams g{};
+        g.A = J.ov.b_ia + (long)c0 * J.n + (long)J.i0 * J.nv;
+        g.B = w.xa.p;
+        g.C = w.q.p;
+        g.M = J.no_a;
+        g.N = J.nvec * J.no_a;
+        g.K = J.nv_a;
+        g.np = 1;
+        g.pps = 1;
+        g.nz2 = 1;
+        g.lda = J.nv;
+        g.ldb = J.nv_a;
+        g.ldc = (long)J.nvec * J.no_a;
+        g.sA1 = J.n;
+        g.sC1 = J.q_per_p;
+        g.alpha = 1.0;
+        g.mode = GEMM_STORE;
+        ps.flops += 2.0 * J.no_a * (double)J.nvec * J.no_a * J.nv_a * pcc;
+        ps.bytes += esz * ((double)pcc * J.no_a * J.nv_a + (double)J.nvec * J.no_a * J.nv_a + (double)pcc * J.q_per_p);
+        plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, pcc, 1, J.nv_a, false, st);
+      }
+      stage.launch(ctx, GF_EXCH_Q, st);
+    }
+    {  // W' += sum_P Q^P B^P_ja (window), B_ja read from the transposed copy
+      Stage<E> stage;
+      ProfScope ps(ctx, st, (pre + "exch_wp").c_str(), 0.0, 0.0);
+      for (JobPlan<E>& J : pl) {
+        if (!J.exch || !J.pair || c >= J.nchunks) continue;
+        const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
+        const bool first = c == 0;
+        OpWork& w = *J.j->work;
+        GemmParams g{};
+        g.A = w.q.p;
+        g.B = J.ov.b_ai + (long)c0 * J.nv * J.no + J.i0;
+        g.C = w.wppart.p;
+        g.M = (int)J.rows;
+        g.N = J.nv_a;
+        g.K = J.no_a;
+        g.np = pcc;
+        g.pps = 1;
+        g.nz2 = 1;
+        g.lda = J.no_a;
+        g.ldb = J.no;
+        g.ldc = J.nv_a;
+        g.sAp = J.q_per_p;
+        g.sBp = (long)J.nv * J.no;
+        g.sCs = J.part_elems;
+        g.alpha = 1.0;
+        g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
+        ps.flops += 2.0 * J.rows * (double)J.nv_a * J.no_a * pcc;
+        ps.bytes += esz * ((double)pcc * J.q_per_p + (double)pcc * J.nv_a * J.no_a) +
+                    asz * J.part_elems * (first ? 1.0 : 2.0);
+        if (first)
+          J.cwp = plan_or_tune<E>(ctx, stage, GF_EXCH_WP, g, J.rows, J.nv_a, 1, pcc, J.no_a, true, st);
+        else
+          stage.add(g, 1, J.cwp);
+      }
+      stage.launch(ctx, GF_EXCH_WP, st);
+    }
+  }
+
+  // 4. combine in f64
+  ProfScope ps(ctx, st, (pre + "combine").c_str(), 0.0, 0.0);
+  for (JobPlan<E>& J : pl) {
+    OpJob* j = J.j;
+    OpWork& w = *j->work;
+    const int ns_w = J.exch ? J.cw.nsub : 0;
+    const int ns_wp = (J.exch && J.pair) ? J.cwp.nsub : 0;
+    CombineArgs cb{};
+    cb.x = j->x;
+    cb.de = j->P->de.as<double>();
+    cb.j = J.naux_j > 0 ? w.jbuf.as<double>() : nullptr;
+    cb.y = j->y;
+    cb.y2 = j->y2;
+    cb.nvec = J.nvec;
+    cb.no = J.no;
+    cb.nv = J.nv;
+    cb.i0 = J.i0;
+    cb.no_a = J.no_a;
+    cb.nv_a = J.nv_a;
+    cb.ns_w = ns_w;
+    cb.ns_wp = ns_wp;
+    cb.sstride = J.part_elems;
+    cb.cj = J.pair ? 4.0 : 2.0;
+    cb.a_x = j->P->a_x;
+    cb.pair = J.pair ? 1 : 0;
+    ps.bytes += 8.0 * J.nvec * J.n * (J.pair ? 5.0 : 3.0) + asz * (ns_w + ns_wp) * J.part_elems;
+    combine<Acc>(cb, J.exch ? w.wpart.as<Acc>() : nullptr, (J.exch && J.pair) ? w.wppart.as<Acc>() : nullptr, st);
+  }
+}
+
+}  // namespace
+
+void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st) {
+  for (int prec = PREC_F64; prec <= PREC_BF16; ++prec)
+    for (int r = 0; r < 2; ++r) {
+      const bool ris = r == 1;
+      std::vector<OpJob*> sel;
+      for (int i = 0; i < n; ++i) {
+        OpJob* j = jobs[i];
+        const bool jr = j->kind == OPK_T || j->kind == OPK_TPAIR;
+        if (j->prec == prec && jr == ris && j->nvec > 0) sel.push_back(j);
+      }
+      if (sel.empty()) continue;
+      if (prec == PREC_F64)
+        run_group<double>(ctx, sel, ris, st);
+      else if (prec == PREC_F32)
+        run_group<float>(ctx, sel, ris, st);
+      else
+        run_group<uint16_t>(ctx, sel, ris, st);
+    }
+}
+
 void apply_operator(rid_problem* P, int kind, int prec, int nvec, const double* x, double* y, double* y2) {
   check_operator(P, kind, prec);
   if (nvec <= 0) return;
-  const bool ris = kind == OPK_T || kind == OPK_TPAIR;
-  const bool pair = kind == OPK_PAIR || kind == OPK_TPAIR;
-  // the outer operator uses every row and the full orbital ranges
-  const int naux_j = ris ? P->naux_ris : P->naux;
-  const int naux_k = ris ? P->naux_ris_k : P->naux;
-  const int i0 = ris ? P->i0 : 0;
-  const int no_a = ris ? P->no - P->i0 : P->no;
-  const int nv_a = ris ? P->nv_act : P->nv;
-  if (prec == PREC_F64) {
-    P->ensure_f64_aux();
-    OpView<double> ov;
-    ov.b_ia = ris ? P->bris_ia : P->b_ia;
-    ov.b_ij = ris ? P->bris_ij : P->b_ij;
-    ov.b_ab = ris ? P->bris_ab : P->b_ab;
-    ov.b_ai = ris ? P->bris_ai64.as<double>() : P->b_ai64.as<double>();
-    ov.naux_j = naux_j;
-    ov.naux_k = naux_k;
-    ov.i0 = i0;
-    ov.no_a = no_a;
-    ov.nv_a = nv_a;
-    ov.ris = ris;
-    run_operator<double>(P, ov, pair, nvec, x, y, y2);
-  } else if (prec == PREC_F32) {
-    RID_CHECK(!ris, RID_ERR_DTYPE, "the ris operators run in FP64 or BF16");
-    P->ensure_f32();
-    OpView<float> ov;
-    ov.b_ia = P->b_ia32.as<float>();
-    ov.b_ij = P->b_ij32.as<float>();
-    ov.b_ab = P->b_ab32.as<float>();
-    ov.b_ai = P->b_ai32.as<float>();
-    ov.naux_j = naux_j;
-    ov.naux_k = naux_k;
-    ov.i0 = i0;
-    ov.no_a = no_a;
-    ov.nv_a = nv_a;
-    ov.ris = ris;
-    run_operator<float>(P, ov, pair, nvec, x, y, y2);
-  } else {
-    P->ensure_bf16();
-    OpView<uint16_t> ov;
-    ov.b_ia = P->bris_ia16.as<uint16_t>();
-    ov.b_ij = P->bris_ij16.as<uint16_t>();
-    ov.b_ab = P->bris_ab16.as<uint16_t>();
-    ov.b_ai = P->bris_ai16.as<uint16_t>();
-    ov.naux_j = naux_j;
-    ov.naux_k = naux_k;
-    ov.i0 = i0;
-    ov.no_a = no_a;
-    ov.nv_a = nv_a;
-    ov.ris = ris;
-    run_operator<uint16_t>(P, ov, pair, nvec, x, y, y2);
+  OpJob j;
+  j.P = P;
+  j.kind = kind;
+  j.prec = prec;
+  j.nvec = nvec;
+  j.x = x;
+  j.y = y;
+  j.y2 = y2;
+  j.work = &P->work;
+  j.stream = P->ctx->stream;
+  OpJob* jp = &j;
+  run_jobs(P->ctx, &jp, 1, P->ctx->stream);
+}
+
+Batcher::Batcher(rid_context* ctx) : ctx_(ctx) {
+  RID_HIP(hipSetDevice(ctx->device));
+  RID_HIP(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+  events_.resize(64, nullptr);
+  for (hipEvent_t& e : events_) RID_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  thread_ = std::thread([this] { loop(); });
+}
+
+Batcher::~Batcher() {
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  if (thread_.joinable()) thread_.join();
+  (void)hipStreamSynchronize(st_);
+  for (hipEvent_t e : events_)
+    if (e) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(st_);
+}
+
+void Batcher::apply(OpJob& j) {
+  j.finished = false;
+  j.code = 0;
+  j.msg.clear();
+  RID_HIP(hipEventRecord(j.ready, j.stream));
+  std::unique_lock<std::mutex> lk(mu_);
+  pending_.push_back(&j);
+  cv_.notify_all();
+  cv_done_.wait(lk, [&] { return j.finished; });
+  if (j.code != 0) throw Error((rid_status)j.code, j.msg);
+}
+
+void Batcher::loop() {
+  (void)hipSetDevice(ctx_->device);
+  std::unique_lock<std::mutex> lk(mu_);
+  while (true) {
+    cv_.wait(lk, [&] { return stop_ || !pending_.empty(); });
+    if (pending_.empty()) {
+      if (stop_) return;
+      continue;
+    }
+    std::vector<OpJob*> batch;
+    batch.swap(pending_);
+    lk.unlock();
+    int code = 0;
+    std::string msg;
+    try {
+      for (OpJob* j : batch) RID_HIP(hipStreamWaitEvent(st_, j->ready, 0));
+      run_jobs(ctx_, batch.data(), (int)batch.size(), st_);
+      hipEvent_t done = events_[next_event_];
+      next_event_ = (next_event_ + 1) % (int)events_.size();
+      RID_HIP(hipEventRecord(done, st_));
+      for (OpJob* j : batch) RID_HIP(hipStreamWaitEvent(j->stream, done, 0));
+    } catch (const Error& e) {
+      code = e.code;
+      msg = e.what();
+    } catch (const std::exception& e) {
+      code = RID_ERR_INTERNAL;
+      msg = e.what();
+    }
+    lk.lock();
+    rounds_ += 1;
+    jobs_ += (int64_t)batch.size();
+    for (OpJob* j : batch) {
+      j->code = code;
+      j->msg = msg;
+      j->finished = true;
+    }
+    cv_done_.notify_all();
   }
 }
 
@@ -571,44 +889,74 @@ uint64_t rid_problem::footprint() const {
 }
 
 void rid_problem::ensure_f64_aux() {
+  std::lock_guard<std::mutex> g(mu);
   hipStream_t st = ctx->stream;
-  if (!b_ai64.p) {
+  bool work = false;
+  if (b_dt == RID_F64 && !b_ai64.p) {
     b_ai64.ensure(sizeof(double) * (size_t)naux * no * nv);
-    rid::transpose_slices<double>(b_ia, naux, no, nv, b_ai64.as<double>(), st);
+    rid::transpose_slices<double, double>(b_ia, naux, no, nv, b_ai64.as<double>(), st);
+    work = true;
   }
-  if (bris_ia && naux_ris_k > 0 && !bris_ai64.p) {
+  if (bris_dt == RID_F64 && bris_ia && naux_ris_k > 0 && !bris_ai64.p) {
     bris_ai64.ensure(sizeof(double) * (size_t)naux_ris_k * no * nv);
-    rid::transpose_slices<double>(bris_ia, naux_ris_k, no, nv, bris_ai64.as<double>(), st);
+    rid::transpose_slices<double, double>(bris_ia, naux_ris_k, no, nv, bris_ai64.as<double>(), st);
+    work = true;
   }
+  // the copies are read from other streams too
+  if (work) RID_HIP(hipStreamSynchronize(st));
 }
 
 void rid_problem::ensure_f32() {
+  std::lock_guard<std::mutex> g(mu);
   hipStream_t st = ctx->stream;
-  if (b_ia32.p) return;
+  if (b_ai32.p) return;
   const long n = (long)no * nv;
-  b_ia32.ensure(sizeof(float) * naux * n);
-  rid::cast_copy<float>(b_ia, naux * n, b_ia32.as<float>(), st);
-  b_ij32.ensure(sizeof(float) * (size_t)naux * no * no);
-  rid::cast_copy<float>(b_ij, (long)naux * no * no, b_ij32.as<float>(), st);
-  b_ab32.ensure(sizeof(float) * (size_t)naux * nv * nv);
-  rid::cast_copy<float>(b_ab, (long)naux * nv * nv, b_ab32.as<float>(), st);
-  b_ai32.ensure(sizeof(float) * naux * n);
-  rid::transpose_slices<float>(b_ia, naux, no, nv, b_ai32.as<float>(), st);
+  if (b_dt == RID_F64) {
+    b_ia32.ensure(sizeof(float) * naux * n);
+    rid::cast_copy<double, float>(b_ia, naux * n, b_ia32.as<float>(), st);
+    b_ij32.ensure(sizeof(float) * (size_t)naux * no * no);
+    rid::cast_copy<double, float>(b_ij, (long)naux * no * no, b_ij32.as<float>(), st);
+    b_ab32.ensure(sizeof(float) * (size_t)naux * nv * nv);
+    rid::cast_copy<double, float>(b_ab, (long)naux * nv * nv, b_ab32.as<float>(), st);
+    b_ai32.ensure(sizeof(float) * naux * n);
+    rid::transpose_slices<double, float>(b_ia, naux, no, nv, b_ai32.as<float>(), st);
+  } else {
+    b_ai32.ensure(sizeof(float) * naux * n);
+    rid::transpose_slices<float, float>(b_ia_f, naux, no, nv, b_ai32.as<float>(), st);
+  }
+  RID_HIP(hipStreamSynchronize(st));
 }
 
 void rid_problem::ensure_bf16() {
+  std::lock_guard<std::mutex> g(mu);
   hipStream_t st = ctx->stream;
   if (bris_ia16.p) return;
   const long n = (long)no * nv;
-  bris_ia16.ensure(2 * naux_ris * n);
-  rid::cast_copy<uint16_t>(bris_ia, naux_ris * n, bris_ia16.as<uint16_t>(), st);
   const int nk = std::max(naux_ris_k, 1);
+  bris_ia16.ensure(2 * naux_ris * n);
   bris_ij16.ensure(2 * (size_t)nk * no * no);
   bris_ab16.ensure(2 * (size_t)nk * nv * nv);
   bris_ai16.ensure(2 * (size_t)nk * n);
-  if (naux_ris_k > 0) {
-    rid::cast_copy<uint16_t>(bris_ij, (long)naux_ris_k * no * no, bris_ij16.as<uint16_t>(), st);
-    rid::cast_copy<uint16_t>(bris_ab, (long)naux_ris_k * nv * nv, bris_ab16.as<uint16_t>(), st);
-    rid::transpose_slices<uint16_t>(bris_ia, naux_ris_k, no, nv, bris_ai16.as<uint16_t>(), st);
+  if (bris_dt == RID_F64) {
+    rid::cast_copy<double, uint16_t>(bris_ia, naux_ris * n, bris_ia16.as<uint16_t>(), st);
+    if (naux_ris_k > 0) {
+      rid::cast_copy<double, uint16_t>(bris_ij, (long)naux_ris_k * no * no, bris_ij16.as<uint16_t>(), st);
+      rid::cast_copy<double, uint16_t>(bris_ab, (long)naux_ris_k * nv * nv, bris_ab16.as<uint16_t>(), st);
+      rid::transpose_slices<double, uint16_t>(bris_ia, naux_ris_k, no, nv, bris_ai16.as<uint16_t>(), st);
+    }
+  } else {
+    rid::cast_copy<float, uint16_t>(bris_ia_f, naux_ris * n, bris_ia16.as<uint16_t>(), st);
+    if (naux_ris_k > 0) {
+      rid::cast_copy<float, uint16_t>(bris_ij_f, (long)naux_ris_k * no * no, bris_ij16.as<uint16_t>(), st);
+      rid::cast_copy<float, uint16_t>(bris_ab_f, (long)naux_ris_k * nv * nv, bris_ab16.as<uint16_t>(), st);
+      rid::transpose_slices<float, uint16_t>(bris_ia_f, naux_ris_k, no, nv, bris_ai16.as<uint16_t>(), st);
+    }
   }
+  RID_HIP(hipStreamSynchronize(st));
+}
+
+rid_context::~rid_context() {
+  delete ring;
+  ring = nullptr;
+  rid::flush_graveyard(this);
 }

@@ -2,7 +2,9 @@
 // operator driver.  Internal C++ (no exceptions cross the C ABI).
 #pragma once
 
+#include <condition_variable>
 #include <map>
+#include <thread>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -23,14 +25,15 @@ struct Profiler {
     double ms = 0.0, flops = 0.0, bytes = 0.0;
   };
   bool on = false;
+  std::mutex mu;  // solves on several host threads share the profiler
   std::vector<std::string> names;
   std::map<std::string, int> ids;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   std::vector<Acc> acc;
-  int family(const char* name);
-  hipEvent_t get_event();
-  void resolve();  // stream must be idle
+  int family(const char* name);   // caller holds mu
+  hipEvent_t get_event();         // caller holds mu
+  void resolve();  // streams must be idle
   ~Profiler();
 };
 
@@ -53,6 +56,9 @@ struct TuneVal {
   int cfg, nsub, pps;
 };
 
+struct DescRing;
+class Batcher;
+
 }  // namespace rid
 
 struct rid_context {
@@ -61,9 +67,19 @@ struct rid_context {
   rid_allocator alloc{};
   bool user_alloc = false;
   std::string last_error;
-  std::mutex mu;  // guards allocator use from the server thread
+  std::mutex mu;  // guards allocator use from several host threads
   rid::Profiler prof;
+  std::mutex tune_mu;
   std::map<rid::TuneKey, rid::TuneVal> tune;
+  // While solves run on several streams (batched solves, the server), freed
+  // device buffers are parked here and released after a device-wide
+  // synchronisation, since the stream that last used them is not known.
+  int defer_free = 0;  // nesting count, guarded by grave_mu
+  std::mutex grave_mu;
+  std::vector<void*> graveyard;
+  uint64_t grave_bytes = 0;
+  rid::DescRing* ring = nullptr;  // grouped-GEMM descriptor staging
+  ~rid_context();
 };
 
 namespace rid {
@@ -71,10 +87,11 @@ namespace rid {
 // RAII bracket of one launch (no-op unless profiling is enabled).
 struct ProfScope {
   rid_context* ctx;
+  hipStream_t st;
   int fam = -1;
   hipEvent_t a = nullptr;
   double flops, bytes;
-  ProfScope(rid_context* c, const char* name, double fl, double by);
+  ProfScope(rid_context* c, hipStream_t s, const char* name, double fl, double by);
   ~ProfScope();
 };
 
@@ -84,6 +101,14 @@ namespace rid {
 
 void* dev_alloc(rid_context* ctx, size_t bytes);
 void dev_free(rid_context* ctx, void* p);
+// Release parked buffers (synchronises the device when there are any).
+void flush_graveyard(rid_context* ctx);
+// Scope in which buffer releases are deferred (see rid_context::graveyard).
+struct DeferFree {
+  rid_context* ctx;
+  explicit DeferFree(rid_context* c);
+  ~DeferFree();
+};
 
 // Owning device buffer from the context's allocator.
 struct DevBuf {
@@ -138,6 +163,12 @@ struct rid_problem {
   // borrowed f64 tensors
   const double *b_ia = nullptr, *b_ij = nullptr, *b_ab = nullptr;
   const double *bris_ia = nullptr, *bris_ij = nullptr, *bris_ab = nullptr;
+  // borrowed f32 tensors (b_dtype / bris_dtype RID_F32 instead of the f64 ones)
+  int b_dt = RID_F64, bris_dt = RID_F64;
+  const float *b_ia_f = nullptr, *b_ij_f = nullptr, *b_ab_f = nullptr;
+  const float *bris_ia_f = nullptr, *bris_ij_f = nullptr, *bris_ab_f = nullptr;
+  bool has_ris() const { return naux_ris > 0 && (bris_ia || bris_ia_f); }
+  std::mutex mu;  // guards the lazily built copies
   // owned
   rid::DevBuf de, b_ai64, bris_ai64;
   rid::DevBuf b_ia32, b_ij32, b_ab32, b_ai32;
@@ -152,6 +183,10 @@ struct rid_problem {
   void ensure_f64_aux();
   void ensure_f32();
   void ensure_bf16();
+  // f32 views of the full tensors (borrowed or cast copies; ensure_f32 first)
+  const float* ia32() const { return b_dt == RID_F32 ? b_ia_f : b_ia32.as<float>(); }
+  const float* ij32() const { return b_dt == RID_F32 ? b_ij_f : b_ij32.as<float>(); }
+  const float* ab32() const { return b_dt == RID_F32 ? b_ab_f : b_ab32.as<float>(); }
 };
 
 namespace rid {
@@ -161,7 +196,55 @@ enum OpKind { OPK_A = 0, OPK_PAIR = 1, OPK_T = 2, OPK_TPAIR = 3 };
 enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 
 // y (and y2 for the pair kinds) = op(x) for nvec vectors; x, y, y2 f64 device.
+// Runs on the context stream with the problem's own scratch.
 void apply_operator(rid_problem* P, int kind, int prec, int nvec, const double* x, double* y, double* y2);
+
+// One operator product request.
+struct OpJob {
+  rid_problem* P = nullptr;
+  int kind = 0, prec = 0, nvec = 0;
+  const double* x = nullptr;
+  double* y = nullptr;
+  double* y2 = nullptr;
+  OpWork* work = nullptr;       // scratch of the requesting solve
+  hipStream_t stream = nullptr; // stream of the requesting solve
+  // set by the Batcher
+  hipEvent_t ready = nullptr;
+  bool finished = false;
+  int code = 0;
+  std::string msg;
+};
+
+// Run the products of several jobs on stream st.  Every GEMM stage of all
+// jobs goes out as one grouped launch per tile configuration; each job's
+// result is what it would be alone.  Jobs must have been checked.
+void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st);
+
+// Collects operator products from solves running on several host threads
+// and streams, and runs whatever is waiting as one grouped product on its
+// own stream, from a thread of its own.  apply() returns once the product
+// is enqueued: the caller's stream waits for it with an event.
+class Batcher {
+ public:
+  explicit Batcher(rid_context* ctx);
+  ~Batcher();
+  void apply(OpJob& j);  // throws rid::Error when the product failed
+  int64_t rounds() const { return rounds_; }
+  int64_t jobs() const { return jobs_; }
+
+ private:
+  void loop();
+  rid_context* ctx_;
+  hipStream_t st_ = nullptr;
+  std::mutex mu_;
+  std::condition_variable cv_, cv_done_;
+  std::vector<OpJob*> pending_;
+  bool stop_ = false;
+  int64_t rounds_ = 0, jobs_ = 0;
+  std::vector<hipEvent_t> events_;
+  int next_event_ = 0;
+  std::thread thread_;
+};
 
 // Validate (kind, prec) combinations; throws rid::Error.
 void check_operator(const rid_problem* P, int kind, int prec);

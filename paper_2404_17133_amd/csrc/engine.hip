@@ -38,7 +38,7 @@ double ms_since(Clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
 
-// Per-solve device context: stream, scratch and transfers.
+// Per-solve device context: stream, scratch, transfers and operator products.
 struct Eng {
   rid_problem* P;
   hipStream_t st;
@@ -46,9 +46,45 @@ struct Eng {
   DevBuf part, tmp1, tmp2, ints, dscal;
   SolveStats* stats;
   uint64_t live = 0;
-  explicit Eng(rid_problem* p, SolveStats* s)
-      : P(p), st(p->ctx->stream), N(p->n()), part(p->ctx), tmp1(p->ctx), tmp2(p->ctx), ints(p->ctx),
-        dscal(p->ctx), stats(s) {}
+  Batcher* batcher;
+  OpWork own;     // operator scratch of a solve that shares the device
+  hipEvent_t ready = nullptr;
+  Eng(rid_problem* p, SolveStats* s, const ExecCfg& ex)
+      : P(p), st(ex.stream ? ex.stream : p->ctx->stream), N(p->n()), part(p->ctx), tmp1(p->ctx), tmp2(p->ctx),
+        ints(p->ctx), dscal(p->ctx), stats(s), batcher(ex.batcher), own(p->ctx) {
+    if (batcher) RID_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  }
+  ~Eng() {
+    if (ready) {
+      (void)hipStreamSynchronize(st);
+      (void)hipEventDestroy(ready);
+    }
+  }
+  Eng(const Eng&) = delete;
+  Eng& operator=(const Eng&) = delete;
+  // y (, y2) = op(x) for nvec vectors, ordered on the solve's stream
+  void apply(int kind, int prec, int nvec, const double* x, double* y, double* y2) {
+    check_operator(P, kind, prec);
+    if (nvec <= 0) return;
+    OpJob j;
+    j.P = P;
+    j.kind = kind;
+    j.prec = prec;
+    j.nvec = nvec;
+    j.x = x;
+    j.y = y;
+    j.y2 = y2;
+    j.stream = st;
+    if (batcher) {
+      j.work = &own;
+      j.ready = ready;
+      batcher->apply(j);
+    } else {
+      j.work = &P->work;
+      OpJob* jp = &j;
+      run_jobs(P->ctx, &jp, 1, st);
+    }
+  }
   RedScratch rs(int m, int n) {
     size_t need = std::max(gram_part_elems(m, n, N), (size_t)256 * std::max(n, 1));
     need = std::max(need, (size_t)256 * std::max(m, 1));
@@ -111,7 +147,7 @@ struct Basis {
 // basis and each other, append the accepted ones.  Returns the number added.
 int append_orthonormal(Eng& E, Basis& B, double* W, int nnew, double drop_tol = 1e-8) {
   if (nnew <= 0) return 0;
-  ProfScope ps(E.P->ctx, "orthonormalize", 0.0, 0.0);
+  ProfScope ps(E.P->ctx, E.st, "orthonormalize", 0.0, 0.0);
   const long N = E.N;
   RID_CHECK(B.m + nnew <= B.cap, RID_ERR_INTERNAL, "basis capacity exceeded");
   E.tmp1.ensure(sizeof(double) * (size_t)std::max(B.m, 1) * nnew + 64 * sizeof(double));
@@ -164,7 +200,7 @@ void multiply(Eng& E, Basis& B, int m0, int kind, int prec, double& t_acc) {
   const int nn = B.m - m0;
   if (nn <= 0) return;
   auto t0 = Clock::now();
-  apply_operator(E.P, kind, prec, nn, B.V(m0), B.P1(m0), B.nprod == 2 ? B.P2(m0) : nullptr);
+  E.apply(kind, prec, nn, B.V(m0), B.P1(m0), B.nprod == 2 ? B.P2(m0) : nullptr);
   E.sync();
   t_acc += ms_since(t0);
 }
@@ -174,7 +210,7 @@ void project(Eng& E, Basis& B, int m0) {
   const int m = B.m, nn = m - m0;
   if (nn <= 0) return;
   const long N = E.N;
-  ProfScope ps(E.P->ctx, "project", 4.0 * m * nn * (double)N * B.nprod, 8.0 * 2 * (m + nn) * (double)N * B.nprod);
+  ProfScope ps(E.P->ctx, E.st, "project", 4.0 * m * nn * (double)N * B.nprod, 8.0 * 2 * (m + nn) * (double)N * B.nprod);
   DevBuf c1(E.P->ctx), c2(E.P->ctx);
   c1.ensure(sizeof(double) * (size_t)m * nn);
   c2.ensure(sizeof(double) * (size_t)m * nn);
@@ -222,7 +258,7 @@ void ritz_sym(Eng& E, Ritz& R, Basis& B, int nq) {
   R.q.ensure(sizeof(double) * (size_t)m * nq);
   R.work.ensure(sizeof(double) * small_syevx_work(m, nq));
   R.ldq = nq;
-  ProfScope ps(E.P->ctx, "small_dense", 0.0, 0.0);
+  ProfScope ps(E.P->ctx, E.st, "small_dense", 0.0, 0.0);
   copy_block(B.a1.as<double>(), B.cap, m, m, R.acopy.as<double>(), m, E.st);
   small_syevx(R.acopy.as<double>(), m, m, nq, R.w.as<double>(), R.q.as<double>(), nq, R.work.as<double>(), E.st);
 }
@@ -263,7 +299,7 @@ void ritz_rpa(Eng& E, Ritz& R, Basis& B, int k, std::vector<double>& w2_host, in
   R.om.ensure(sizeof(double) * 3 * kk);
   R.info.ensure(sizeof(int) * 4);
   {
-  ProfScope ps(E.P->ctx, "small_dense", 0.0, 0.0);
+  ProfScope ps(E.P->ctx, E.st, "small_dense", 0.0, 0.0);
   copy_block(B.a2.as<double>(), B.cap, m, m, R.lmat.as<double>(), m, E.st);
   small_chol(R.lmat.as<double>(), m, m, R.info.as<int>(), E.st);
   // M = L^T a_+ L
@@ -350,7 +386,7 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
       gram(rh.as<double>(), N, nr, U.V(0), N, m, N, gbuf.as<double>(), m, rs, E.st);  // g[n][i]
     }
     {
-      ProfScope ps(E.P->ctx, "inner_solve", 0.0, 0.0);
+      ProfScope ps(E.P->ctx, E.st, "inner_solve", 0.0, 0.0);
       build_shifted(U.a1.as<double>(), nullptr, m, U.cap, sh, nr, 0, mats.as<double>(), E.st);
       small_lu_solve(mats.as<double>(), gbuf.as<double>(), m, nr, E.st);  // y[n][i]
     }
@@ -399,7 +435,7 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
 // the full 2m x 2m systems are solved instead.
 void solve_pair_systems(Eng& E, Basis& U, int m, const double* sh, int nb, double* g, DevBuf& mats, DevBuf& work) {
   const int d = 2 * m;
-  ProfScope ps(E.P->ctx, "inner_solve", 0.0, 0.0);
+  ProfScope ps(E.P->ctx, E.st, "inner_solve", 0.0, 0.0);
   work.ensure(sizeof(double) * ((size_t)3 * m * m + (size_t)2 * nb * m + 8));
   double* L = work.as<double>();
   double* G = L + (size_t)m * m;
@@ -765,17 +801,22 @@ void validate_opts(const rid_solve_opts& o, const rid_problem* P) {
             "iteration limits must be >= 1");
   RID_CHECK(o.m_max >= 0 && o.m_max <= 1000, RID_ERR_INVALID_ARG, "m_max must be in [0, 1000]");
   if (o.precond == RID_PRECOND_RIS)
-    RID_CHECK(P->naux_ris > 0 && P->bris_ia, RID_ERR_INVALID_ARG, "ris preconditioner needs a ris tensor");
+    RID_CHECK(P->has_ris(), RID_ERR_INVALID_ARG, "ris preconditioner needs a ris tensor");
+  if (o.precision == RID_PRECISION_FP64) {
+    RID_CHECK(P->b_dt == RID_F64, RID_ERR_DTYPE, "an FP64 solve needs FP64 tensors");
+    if (o.precond == RID_PRECOND_RIS)
+      RID_CHECK(P->bris_dt == RID_F64, RID_ERR_DTYPE, "an FP64 solve with the ris model needs FP64 ris tensors");
+  }
 }
 
 rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode, double* omega_host, double* x_dev,
-                       double* y_dev, double* resid_host, SolveStats& st) {
+                       double* y_dev, double* resid_host, SolveStats& st, const ExecCfg& ex) {
   validate_opts(o, P);
   const long N = P->n();
   RID_CHECK(k >= 1 && k <= N, RID_ERR_SHAPE, "k must be in [1, N]");
   RID_CHECK(mode == RID_TDA || mode == RID_RPA, RID_ERR_INVALID_ARG, "bad mode");
   auto t_all = Clock::now();
-  Eng E(P, &st);
+  Eng E(P, &st, ex);
   rid_context* ctx = P->ctx;
   const bool ris = o.precond == RID_PRECOND_RIS;
   const int extra = o.n_extra_init >= 0 ? o.n_extra_init : (ris ? std::min(k, 3) : 8);
@@ -936,7 +977,7 @@ rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode,
 
 rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, const double* p_dev, int nfreq,
                           const double* omega_host, double* alpha_host, double* u_dev, double* resid_host,
-                          SolveStats& st) {
+                          SolveStats& st, const ExecCfg& ex) {
   validate_opts(o, P);
   RID_CHECK(nrhs >= 1 && nfreq >= 1, RID_ERR_SHAPE, "nrhs and nfreq must be >= 1");
   RID_CHECK(p_dev && omega_host && alpha_host, RID_ERR_INVALID_ARG, "null argument");
@@ -947,7 +988,7 @@ rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, con
               "frequency within the guard of the lowest orbital energy difference");
   }
   auto t_all = Clock::now();
-  Eng E(P, &st);
+  Eng E(P, &st, ex);
   rid_context* ctx = P->ctx;
   const long N = P->n();
   const bool ris = o.precond == RID_PRECOND_RIS;

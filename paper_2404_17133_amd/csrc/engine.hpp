@@ -14,14 +14,23 @@ struct SolveStats {
   uint64_t peak_bytes = 0;
 };
 
+// Where a solve runs: its stream (null: the context stream) and, for solves
+// that share the device with others, the Batcher that groups their operator
+// products (null: products run directly on the solve's stream with the
+// problem's scratch).
+struct ExecCfg {
+  hipStream_t stream = nullptr;
+  Batcher* batcher = nullptr;
+};
+
 // k lowest roots; TDA (mode 0) or full TDDFT (mode 1).  Returns RID_OK,
 // RID_WARN_NOT_CONVERGED or throws rid::Error.
 rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode, double* omega_host, double* x_dev,
-                       double* y_dev, double* resid_host, SolveStats& st);
+                       double* y_dev, double* resid_host, SolveStats& st, const ExecCfg& ex = ExecCfg());
 
 rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, const double* p_dev, int nfreq,
                           const double* omega_host, double* alpha_host, double* u_dev, double* resid_host,
-                          SolveStats& st);
+                          SolveStats& st, const ExecCfg& ex = ExecCfg());
 
 void validate_opts(const rid_solve_opts& o, const rid_problem* P);
 

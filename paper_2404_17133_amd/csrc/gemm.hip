@@ -14,6 +14,8 @@
 // use the same permutation the sum over K is unchanged.
 #include "gemm.hpp"
 
+#include <algorithm>
+
 namespace rid {
 namespace {
 
@@ -89,8 +91,12 @@ struct MinBlocks<double> {
   static constexpr int value = 1;
 };
 
-template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
-__global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmParams p) {
+// One BM x BN output tile (tm, tn) of batch z and split `split`.  Shared by
+// the single-GEMM and the grouped kernels, so that a tile's arithmetic does
+// not depend on which kernel runs it.  Ends with every wave past the last
+// read of its LDS buffers, so that the next tile may refill them.
+template <typename T, int BM, int BN, int WM, int WN, bool VEC>
+__device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, int z, int split) {
   using At = Atom<T>;
   using E_t = typename At::elem_t;
   using V_t = typename At::vec_t;
@@ -115,11 +121,6 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmP
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int tiles_m = (p.M + BM - 1) / BM;
-  const int tm = blockIdx.x % tiles_m;
-  const int tn = blockIdx.x / tiles_m;
-  const int z = blockIdx.y;
-  const int split = blockIdx.z;
   const int m0 = tm * BM;
   const int n0 = tn * BN;
   const int z1 = z / p.nz2, z2 = z % p.nz2;
@@ -132,6 +133,10 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmP
 
   const int kc = tid & 7;
   const int rbase = tid >> 3;
+  // operand strides as plain values (selecting between fields of a local
+  // copy of p would put that copy in scratch memory)
+  const long lda = p.lda, ldb = p.ldb, sAp = p.sAp, sBp = p.sBp;
+  const int M = p.M, N = p.N, K = p.K;
 
   auto gload = [&](int t, uint4 (&pre)[CPT]) {
     const int pp = pbeg + t / nkt;
@@ -143,19 +148,19 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmP
       bool ok;
       if (r < BM) {
         const int m = m0 + r;
-        ok = m < p.M;
-        src = Ab + pp * p.sAp + (long)m * p.lda + k;
+        ok = m < M;
+        src = Ab + pp * sAp + (long)m * lda + k;
       } else {
         const int n = n0 + (r - BM);
-        ok = n < p.N;
-        src = Bb + pp * p.sBp + (long)n * p.ldb + k;
+        ok = n < N;
+        src = Bb + pp * sBp + (long)n * ldb + k;
       }
       if constexpr (VEC) {
-        pre[i] = (ok && k < p.K) ? *reinterpret_cast<const uint4*>(src) : make_uint4(0, 0, 0, 0);
+        pre[i] = (ok && k < K) ? *reinterpret_cast<const uint4*>(src) : make_uint4(0, 0, 0, 0);
       } else {
         union { uint4 v; E_t e[VW]; } u;
 #pragma unroll
-        for (int e = 0; e < VW; ++e) u.e[e] = (ok && k + e < p.K) ? src[e] : E_t(0);
+        for (int e = 0; e < VW; ++e) u.e[e] = (ok && k + e < K) ? src[e] : E_t(0);
         pre[i] = u.v;
       }
     }
@@ -250,6 +255,37 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmP
   }
 }
 
+template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
+__global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmParams p) {
+  const int tiles_m = (p.M + BM - 1) / BM;
+  gemm_tile<T, BM, BN, WM, WN, VEC>(p, blockIdx.x % tiles_m, blockIdx.x / tiles_m, blockIdx.y, blockIdx.z);
+}
+
+// Device descriptor of one member of a grouped launch.
+struct GroupDesc {
+  GemmParams p;
+  int tiles_m, tiles_mn, nz, pad;
+  long begin;  // index of the member's first tile in the launch
+};
+
+// Persistent grouped GEMM: the workgroups walk the concatenated tile lists of
+// all members (tile fastest, then batch, then split, the order in which the
+// single-GEMM grid is dispatched), each taking every gridDim.x-th tile.
+template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
+__global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_grouped_kernel(const GroupDesc* __restrict__ gd,
+                                                                               int ngroups, long total) {
+  int g = 0;
+  for (long b = blockIdx.x; b < total; b += gridDim.x) {
+    while (g + 1 < ngroups && b >= gd[g + 1].begin) ++g;
+    const GemmParams p = gd[g].p;
+    const long local = b - gd[g].begin;
+    const int tiles_m = gd[g].tiles_m, tiles_mn = gd[g].tiles_mn, nz = gd[g].nz;
+    const int tile = (int)(local % tiles_mn);
+    const long rest = local / tiles_mn;
+    gemm_tile<T, BM, BN, WM, WN, VEC>(p, tile % tiles_m, tile / tiles_m, (int)(rest % nz), (int)(rest / nz));
+  }
+}
+
 struct TileCfg {
   int bm, bn;
 };
@@ -291,12 +327,96 @@ void launch_cfg(const GemmParams& p, int nz, int nsplit, bool vec, hipStream_t s
   }
 }
 
+template <typename T, int BM, int BN, int WM, int WN, bool VEC>
+void launch_grouped_fam(const GroupDesc* gd, int n, long total, int grid, int family, hipStream_t stream) {
+#define RID_GROUPED(F)                                                                                      \
+  hipLaunchKernelGGL((gemm_grouped_kernel<T, BM, BN, WM, WN, VEC, F>), dim3(grid), dim3(256), 0, stream, gd, n, \
+                     total)
+  switch (family) {
+    case GF_COUL: RID_GROUPED(GF_COUL); break;
+    case GF_EXCH_S: RID_GROUPED(GF_EXCH_S); break;
+    case GF_EXCH_W: RID_GROUPED(GF_EXCH_W); break;
+    case GF_EXCH_Q: RID_GROUPED(GF_EXCH_Q); break;
+    case GF_EXCH_WP: RID_GROUPED(GF_EXCH_WP); break;
+    default: RID_GROUPED(GF_GENERIC); break;
+  }
+#undef RID_GROUPED
+}
+
+template <typename T, int BM, int BN, int WM, int WN>
+void launch_grouped_cfg(const GroupDesc* gd, int n, long total, int grid, bool vec, int family, hipStream_t stream) {
+  if (vec)
+    launch_grouped_fam<T, BM, BN, WM, WN, true>(gd, n, total, grid, family, stream);
+  else
+    launch_grouped_fam<T, BM, BN, WM, WN, false>(gd, n, total, grid, family, stream);
+}
+
 template <typename T>
 int elem_size() {
   return std::is_same<T, bf16_t>::value ? 2 : (int)sizeof(T);
 }
 
+template <typename T>
+bool vec_ok(const GemmParams& p) {
+  const int vw = 16 / elem_size<T>();
+  return (p.K % vw == 0) && (p.lda % vw == 0) && (p.ldb % vw == 0) && (p.sAp % vw == 0) && (p.sBp % vw == 0) &&
+         (p.sA1 % vw == 0) && (p.sA2 % vw == 0) && (p.sB1 % vw == 0) && (p.sB2 % vw == 0) &&
+         ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.B % 16 == 0);
+}
+
+void check_params(const GemmParams& p, int nz, int nsplit) {
+  RID_CHECK(p.np >= 1 && p.pps >= 1 && p.nz2 >= 1, RID_ERR_INTERNAL, "gemm: bad batch counts");
+  RID_CHECK((long)nsplit * p.pps >= p.np, RID_ERR_INTERNAL, "gemm: splits do not cover batches");
+  RID_CHECK(ceil_div_l(p.M, 64) * ceil_div_l(p.N, 64) < (1L << 31), RID_ERR_SHAPE, "gemm: grid too large");
+  RID_CHECK(nz < 65536 && nsplit < 65536, RID_ERR_SHAPE, "gemm: batch grid too large");
+}
+
 }  // namespace
+
+size_t gemm_group_desc_bytes(int n) { return sizeof(GroupDesc) * (size_t)std::max(n, 1); }
+
+template <typename T>
+void gemm_grouped(const GemmGroup* mem, int n, int cfg, int family, void* desc_dev, void* desc_host,
+                  hipStream_t stream, int grid_cap) {
+  RID_CHECK(cfg >= 0 && cfg < 3, RID_ERR_INTERNAL, "gemm: bad tile configuration");
+  const int bm = Cfgs<T>::c[cfg].bm, bn = Cfgs<T>::c[cfg].bn;
+  GroupDesc* hd = reinterpret_cast<GroupDesc*>(desc_host);
+  // vector-load members first, then the others: one launch per kind
+  int cnt[2] = {0, 0};
+  long total[2] = {0, 0};
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i < n; ++i) {
+      const GemmParams& p = mem[i].p;
+      if (p.M <= 0 || p.N <= 0 || mem[i].nz <= 0 || mem[i].nsplit <= 0) continue;
+      if (vec_ok<T>(p) != (pass == 0)) continue;
+      check_params(p, mem[i].nz, mem[i].nsplit);
+      GroupDesc& d = hd[cnt[0] + cnt[1]];
+      d.p = p;
+      d.tiles_m = ceil_div(p.M, bm);
+      d.tiles_mn = d.tiles_m * ceil_div(p.N, bn);
+      d.nz = mem[i].nz;
+      d.pad = 0;
+      d.begin = total[pass];
+      total[pass] += (long)d.tiles_mn * mem[i].nz * mem[i].nsplit;
+      ++cnt[pass];
+    }
+  }
+  const int used = cnt[0] + cnt[1];
+  if (used == 0) return;
+  RID_HIP(hipMemcpyAsync(desc_dev, desc_host, sizeof(GroupDesc) * used, hipMemcpyHostToDevice, stream));
+  const GroupDesc* dd = reinterpret_cast<const GroupDesc*>(desc_dev);
+  for (int pass = 0; pass < 2; ++pass) {
+    if (cnt[pass] == 0) continue;
+    const GroupDesc* base = dd + (pass == 0 ? 0 : cnt[0]);
+    const int grid = (int)std::min<long>(total[pass], std::max(grid_cap, 1));
+    switch (cfg) {
+      case 0: launch_grouped_cfg<T, 128, 128, 64, 64>(base, cnt[pass], total[pass], grid, pass == 0, family, stream); break;
+      case 1: launch_grouped_cfg<T, 64, 64, 32, 32>(base, cnt[pass], total[pass], grid, pass == 0, family, stream); break;
+      default: launch_grouped_cfg<T, 128, 64, 64, 32>(base, cnt[pass], total[pass], grid, pass == 0, family, stream); break;
+    }
+    RID_HIP(hipGetLastError());
+  }
+}
 
 template <typename T>
 int gemm_num_configs() {
@@ -311,14 +431,8 @@ void gemm_config_tile(int cfg, int* bm, int* bn) {
 template <typename T>
 void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int cfg, int family) {
   if (p.M <= 0 || p.N <= 0 || nz <= 0 || nsplit <= 0) return;
-  RID_CHECK(p.np >= 1 && p.pps >= 1 && p.nz2 >= 1, RID_ERR_INTERNAL, "gemm: bad batch counts");
-  RID_CHECK((long)nsplit * p.pps >= p.np, RID_ERR_INTERNAL, "gemm: splits do not cover batches");
-  RID_CHECK(ceil_div_l(p.M, 64) * ceil_div_l(p.N, 64) < (1L << 31), RID_ERR_SHAPE, "gemm: grid too large");
-  RID_CHECK(nz < 65536 && nsplit < 65536, RID_ERR_SHAPE, "gemm: batch grid too large");
-  const int vw = 16 / elem_size<T>();
-  const bool vec = (p.K % vw == 0) && (p.lda % vw == 0) && (p.ldb % vw == 0) && (p.sAp % vw == 0) &&
-                   (p.sBp % vw == 0) && (p.sA1 % vw == 0) && (p.sA2 % vw == 0) && (p.sB1 % vw == 0) &&
-                   (p.sB2 % vw == 0) && ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.B % 16 == 0);
+  check_params(p, nz, nsplit);
+  const bool vec = vec_ok<T>(p);
   if (cfg < 0) {
     // default: big tiles when the output is large enough to fill the chip
     const long t128 = ceil_div_l(p.M, 128) * ceil_div_l(p.N, 128) * (long)nz * nsplit;
@@ -332,6 +446,9 @@ void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int cf
   RID_HIP(hipGetLastError());
 }
 
+template void gemm_grouped<double>(const GemmGroup*, int, int, int, void*, void*, hipStream_t, int);
+template void gemm_grouped<float>(const GemmGroup*, int, int, int, void*, void*, hipStream_t, int);
+template void gemm_grouped<bf16_t>(const GemmGroup*, int, int, int, void*, void*, hipStream_t, int);
 template void gemm_nt<double>(const GemmParams&, int, int, hipStream_t, int, int);
 template void gemm_nt<float>(const GemmParams&, int, int, hipStream_t, int, int);
 template void gemm_nt<bf16_t>(const GemmParams&, int, int, hipStream_t, int, int);

@@ -45,6 +45,27 @@ struct bf16_t {};
 template <typename T>
 void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int tile_cfg = -1, int family = GF_GENERIC);
 
+// One member of a grouped launch: a GEMM as gemm_nt(p, nz, nsplit, ...)
+// would run it.
+struct GemmGroup {
+  GemmParams p;
+  int nz, nsplit;
+};
+
+// Bytes of device (and pinned host staging) descriptor memory that a grouped
+// launch of n members needs.
+size_t gemm_group_desc_bytes(int n);
+
+// Run n GEMMs of one element type and tile configuration in one persistent
+// launch (two when some members cannot use 16-byte loads) of at most
+// grid_cap workgroups.  Every member's output is bit for bit what gemm_nt
+// with the same arguments writes: both kernels run the same tile code.  The
+// descriptors are staged in desc_host (pinned) and copied to desc_dev on
+// `stream`; the caller keeps both untouched until that copy has run.
+template <typename T>
+void gemm_grouped(const GemmGroup* members, int n, int tile_cfg, int family, void* desc_dev, void* desc_host,
+                  hipStream_t stream, int grid_cap);
+
 // Number of tile configurations available for T (for the autotuner).
 template <typename T>
 int gemm_num_configs();

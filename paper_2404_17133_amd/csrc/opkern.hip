@@ -119,24 +119,24 @@ __global__ void combine_kernel(CombineArgs c, const A* __restrict__ wp, const A*
   }
 }
 
-template <typename E>
-__global__ void cast_kernel(const double* __restrict__ src, long n, E* __restrict__ dst) {
+template <typename S, typename E>
+__global__ void cast_kernel(const S* __restrict__ src, long n, E* __restrict__ dst) {
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
     dst[t] = to_elem<E>(src[t]);
 }
 
 // dst[p][c][r] = src[p][r][c] for an (rows x cols) slice per p, 32x32 LDS tiles.
-template <typename E>
-__global__ void transpose_kernel(const double* __restrict__ src, int rows, int cols, E* __restrict__ dst) {
-  __shared__ double tile[32][33];
+template <typename S, typename E>
+__global__ void transpose_kernel(const S* __restrict__ src, int rows, int cols, E* __restrict__ dst) {
+  __shared__ S tile[32][33];
   const long p = blockIdx.z;
   const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
-  const double* s = src + p * (long)rows * cols;
+  const S* s = src + p * (long)rows * cols;
   E* d = dst + p * (long)rows * cols;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 32 x 8
   for (int k = ty; k < 32; k += 8) {
     const int r = r0 + k, c = c0 + tx;
-    tile[k][tx] = (r < rows && c < cols) ? s[(long)r * cols + c] : 0.0;
+    tile[k][tx] = (r < rows && c < cols) ? s[(long)r * cols + c] : S(0);
   }
   __syncthreads();
   for (int k = ty; k < 32; k += 8) {
@@ -186,27 +186,29 @@ void combine(const CombineArgs& c, const A* wp, const A* wpp, hipStream_t s) {
   RID_HIP(hipGetLastError());
 }
 
-template <typename E>
-void cast_copy(const double* src, long n, E* dst, hipStream_t s) {
+template <typename S, typename E>
+void cast_copy(const S* src, long n, E* dst, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(cast_kernel<E>, dim3(grid_for(n)), dim3(256), 0, s, src, n, dst);
+  hipLaunchKernelGGL((cast_kernel<S, E>), dim3(grid_for(n)), dim3(256), 0, s, src, n, dst);
   RID_HIP(hipGetLastError());
 }
 
-template <typename E>
-void transpose_slices(const double* src, int np, int rows, int cols, E* dst, hipStream_t s) {
+template <typename S, typename E>
+void transpose_slices(const S* src, int np, int rows, int cols, E* dst, hipStream_t s) {
   if (np == 0 || rows == 0 || cols == 0) return;
   dim3 grid((unsigned)ceil_div(cols, 32), (unsigned)ceil_div(rows, 32), (unsigned)np);
   RID_CHECK(np < 65536 && ceil_div(rows, 32) < 65536, RID_ERR_SHAPE, "transpose: grid too large");
-  hipLaunchKernelGGL(transpose_kernel<E>, grid, dim3(256), 0, s, src, rows, cols, dst);
+  hipLaunchKernelGGL((transpose_kernel<S, E>), grid, dim3(256), 0, s, src, rows, cols, dst);
   RID_HIP(hipGetLastError());
 }
 
 #define RID_INST_E(E)                                                                                   \
   template void prep_x<E>(const double*, int, int, int, int, int, int, E*, E*, E*, hipStream_t);       \
   template void coul_bwd<E>(const double*, const E*, int, long, int, double*, hipStream_t);            \
-  template void cast_copy<E>(const double*, long, E*, hipStream_t);                                     \
-  template void transpose_slices<E>(const double*, int, int, int, E*, hipStream_t);
+  template void cast_copy<double, E>(const double*, long, E*, hipStream_t);                             \
+  template void cast_copy<float, E>(const float*, long, E*, hipStream_t);                               \
+  template void transpose_slices<double, E>(const double*, int, int, int, E*, hipStream_t);             \
+  template void transpose_slices<float, E>(const float*, int, int, int, E*, hipStream_t);
 RID_INST_E(double)
 RID_INST_E(float)
 RID_INST_E(uint16_t)

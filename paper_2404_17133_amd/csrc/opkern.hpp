@@ -29,9 +29,9 @@ template <typename E>
 void coul_bwd(const double* t, const E* b, int naux, long n, int nvec, double* j, hipStream_t s);
 template <typename A>
 void combine(const CombineArgs& c, const A* wp, const A* wpp, hipStream_t s);
-template <typename E>
-void cast_copy(const double* src, long n, E* dst, hipStream_t s);
-template <typename E>
-void transpose_slices(const double* src, int np, int rows, int cols, E* dst, hipStream_t s);
+template <typename S, typename E>
+void cast_copy(const S* src, long n, E* dst, hipStream_t s);
+template <typename S, typename E>
+void transpose_slices(const S* src, int np, int rows, int cols, E* dst, hipStream_t s);
 
 }  // namespace rid

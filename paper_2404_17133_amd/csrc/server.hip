@@ -1,15 +1,29 @@
-// Batched solves and the request server.
+// Batched solves and the continuous-batching request server.
 //
-// The server owns one worker thread.  Submitted requests wait in a FIFO
-// queue; the worker admits a request when a slot is free and its estimated
-// device footprint fits the remaining budget, then runs the admitted requests.
-// Result timestamps (arrival, admission, completion) are in milliseconds on
-// the server's steady clock.
+// Both run several solves at once, each on a host thread and HIP stream of
+// its own, and share one Batcher: whenever solves wait for operator products,
+// the Batcher runs all of them as one grouped product (one persistent grouped
+// GEMM launch per contraction stage and tile shape), so that small molecules
+// share the chip with large ones and the latency-bound steps of one solve
+// (Rayleigh-Ritz, Gram-Schmidt, reads of a few scalars) overlap with the
+// products of the others.  A solve's result does not depend on which other
+// solves run beside it: every grouped launch computes each member's tiles
+// with the same code and plan as a launch of that member alone.
+//
+// The server admits queued requests in arrival order when a slot is free and
+// the request's estimated device footprint fits the remaining budget; a
+// request admitted while others run joins their grouped products at the next
+// round.  Every admitted solve keeps its subspace in device memory until it
+// ends.  Result timestamps (arrival, admission, completion) are in
+// milliseconds on the server's steady clock.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <numeric>
 #include <thread>
 
 #include "engine.hpp"
@@ -21,6 +35,12 @@ namespace {
 typedef std::chrono::steady_clock Clock;
 
 enum ReqState { RQ_QUEUED = 0, RQ_RUNNING = 1, RQ_DONE = 2 };
+
+// Parked device memory above which a finishing solve releases it (this
+// synchronises the device once).
+constexpr uint64_t kFlushBytes = 4ull << 30;
+
+std::mutex g_err_mu;  // last_error is written from several threads
 
 struct Req {
   uint64_t ticket = 0;
@@ -48,27 +68,50 @@ void fill(rid_result* out, const SolveStats& s) {
   o.bytes_resident = s.peak_bytes;
 }
 
-rid_status run_one(rid_problem* P, const rid_request& r, rid_result* res) {
+rid_status run_one(rid_problem* P, const rid_request& r, rid_result* res, const ExecCfg& ex) {
   SolveStats st;
   rid_status s;
   try {
-    RID_HIP(hipSetDevice(P->ctx->device));
     if (r.kind == 0) {
-      s = eigen_solve(P, r.opts, r.k, r.mode, res->omega_host, nullptr, nullptr, res->resid_host, st);
+      s = eigen_solve(P, r.opts, r.k, r.mode, res->omega_host, nullptr, nullptr, res->resid_host, st, ex);
     } else {
       s = response_solve(P, r.opts, r.nrhs, r.p_dev, r.nfreq, r.omega_host, res->alpha_host, nullptr,
-                         res->resid_host, st);
+                         res->resid_host, st, ex);
     }
   } catch (const Error& e) {
+    std::lock_guard<std::mutex> g(g_err_mu);
     P->ctx->last_error = e.what();
     s = e.code;
   } catch (const std::exception& e) {
+    std::lock_guard<std::mutex> g(g_err_mu);
     P->ctx->last_error = e.what();
     s = RID_ERR_INTERNAL;
   }
   fill(res, st);
   res->status = s;
   return s;
+}
+
+// A HIP stream owned by one worker thread.
+struct WorkerStream {
+  hipStream_t s = nullptr;
+  explicit WorkerStream(int device) {
+    RID_HIP(hipSetDevice(device));
+    RID_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  }
+  ~WorkerStream() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  }
+};
+
+// Estimated operator work of a request, for ordering a batch (largest first).
+double request_weight(const rid_problem* P, const rid_request& r) {
+  const double n = (double)P->n();
+  const int k = r.kind == 0 ? r.k : r.nrhs * std::max(r.nfreq, 1);
+  return n * (double)P->naux * (double)(P->no + P->nv) * k;
 }
 
 }  // namespace
@@ -78,7 +121,9 @@ rid_status run_one(rid_problem* P, const rid_request& r, rid_result* res) {
 struct rid_server {
   rid_context* ctx = nullptr;
   rid_server_opts opts{};
-  std::thread worker;
+  std::vector<std::thread> workers;
+  rid::Batcher* batcher = nullptr;
+  rid::DeferFree* defer = nullptr;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<rid::Req*> queue;
@@ -101,18 +146,54 @@ uint64_t request_footprint(const rid_problem* P, const rid_request& r) {
   const int mm = r.opts.m_max > 0 ? r.opts.m_max : std::max(200, 40 * k);
   const uint64_t basis = (uint64_t)(mm + 4 * k + 8) * N * 8 * 3;  // V and two product blocks
   const uint64_t inner = (uint64_t)(2 * k * (r.opts.inner_max_iter + 1)) * N * 8 * 3;
-  const uint64_t tens = (uint64_t)P->naux * (N + (uint64_t)P->no * P->no + (uint64_t)P->nv * P->nv) *
-                        (r.opts.precision == RID_PRECISION_MIXED ? 4 : 0);
+  // FP32 copies of FP64 tensors (none when the caller lends FP32 tensors)
+  const uint64_t tens = (P->b_dt == RID_F64 && r.opts.precision == RID_PRECISION_MIXED)
+                            ? (uint64_t)P->naux * (N + (uint64_t)P->no * P->no + (uint64_t)P->nv * P->nv) * 4
+                            : 0;
   const uint64_t work = (uint64_t)(3 * k) * N * 8 * 6 + (256ull << 20);
   return basis + inner + tens + work;
 }
 
 rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const rid_request* reqs,
                      rid_result* results) {
-  (void)ctx;
+  if (n <= 0) return RID_OK;
+  for (int i = 0; i < n; ++i) {
+    RID_CHECK(probs[i] && probs[i]->ctx == ctx, RID_ERR_INVALID_ARG, "problem of another context");
+    RID_CHECK(reqs[i].kind == 0 || reqs[i].kind == 1, RID_ERR_INVALID_ARG, "bad request kind");
+    results[i].status = RID_ERR_PENDING;
+  }
+  RID_HIP(hipStreamSynchronize(ctx->stream));
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return request_weight(probs[a], reqs[a]) > request_weight(probs[b], reqs[b]);
+  });
+  const int nworkers = std::min(n, 16);
+  std::atomic<int> next{0};
+  {
+    DeferFree defer(ctx);
+    Batcher batcher(ctx);
+    std::vector<std::thread> th;
+    for (int w = 0; w < nworkers; ++w)
+      th.emplace_back([&] {
+        try {
+          WorkerStream ws(ctx->device);
+          const ExecCfg ex{ws.s, &batcher};
+          for (int q = next++; q < n; q = next++) {
+            const int i = order[q];
+            run_one(probs[i], reqs[i], &results[i], ex);
+          }
+        } catch (const Error& e) {
+          std::lock_guard<std::mutex> g(g_err_mu);
+          ctx->last_error = e.what();
+          for (int q = next++; q < n; q = next++) results[order[q]].status = e.code;
+        }
+      });
+    for (std::thread& t : th) t.join();
+  }
   rid_status worst = RID_OK;
   for (int i = 0; i < n; ++i) {
-    const rid_status s = run_one(probs[i], reqs[i], &results[i]);
+    const rid_status s = results[i].status;
     if (s < 0 && worst >= 0) worst = s;
     if (s == RID_WARN_NOT_CONVERGED && worst == RID_OK) worst = s;
   }
@@ -121,53 +202,87 @@ rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const r
 
 namespace {
 
+void finish(rid_server* s, Req* q, rid_status st) {
+  q->state = RQ_DONE;
+  q->res->status = st;
+  q->res->t_done_ms = s->now_ms();
+  s->cv_done.notify_all();
+}
+
+void worker_body(rid_server* s, const ExecCfg& ex);
+
 void worker_loop(rid_server* s) {
+  try {
+    WorkerStream ws(s->ctx->device);
+    worker_body(s, ExecCfg{ws.s, s->batcher});
+  } catch (const std::exception& e) {
+    // no stream for this slot: the other slots serve the queue
+    std::lock_guard<std::mutex> g(g_err_mu);
+    s->ctx->last_error = e.what();
+  }
+}
+
+void worker_body(rid_server* s, const ExecCfg& ex) {
   std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
-    s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-    if (s->stop && s->queue.empty()) return;
-    // admission: FIFO, by slot and footprint
+    // admission: the oldest request, once it fits the remaining budget
+    s->cv_work.wait(lk, [&] {
+      if (s->queue.empty()) return s->stop;
+      Req* h = s->queue.front();
+      return h->cancel || h->bytes > s->opts.hbm_budget_bytes ||
+             s->used_bytes + h->bytes <= s->opts.hbm_budget_bytes;
+    });
+    if (s->queue.empty()) return;  // stop
     Req* q = s->queue.front();
+    s->queue.pop_front();
     if (q->cancel) {
-      s->queue.pop_front();
-      q->state = RQ_DONE;
-      q->res->status = RID_ERR_CANCELLED;
-      q->res->t_done_ms = s->now_ms();
-      s->cv_done.notify_all();
+      finish(s, q, RID_ERR_CANCELLED);
+      s->cv_work.notify_all();
       continue;
     }
     if (q->bytes > s->opts.hbm_budget_bytes) {
-      s->queue.pop_front();
-      q->state = RQ_DONE;
-      q->res->status = RID_ERR_NO_MEMORY;
-      q->res->t_done_ms = s->now_ms();
-      s->cv_done.notify_all();
+      finish(s, q, RID_ERR_NO_MEMORY);
+      s->cv_work.notify_all();
       continue;
     }
-    s->queue.pop_front();
     q->state = RQ_RUNNING;
     q->res->t_admit_ms = s->now_ms();
     s->used_bytes += q->bytes;
     s->running += 1;
+    s->cv_work.notify_all();  // the next request may fit too
     lk.unlock();
-    run_one(q->P, q->r, q->res);
+    const rid_status st = run_one(q->P, q->r, q->res, ex);
+    uint64_t parked;
+    {
+      std::lock_guard<std::mutex> g(s->ctx->grave_mu);
+      parked = s->ctx->grave_bytes;
+    }
     lk.lock();
     s->used_bytes -= q->bytes;
     s->running -= 1;
-    q->res->t_done_ms = s->now_ms();
-    q->state = RQ_DONE;
-    s->cv_done.notify_all();
+    const bool idle = s->running == 0;
+    finish(s, q, st);
+    s->cv_work.notify_all();
+    if (idle || parked > kFlushBytes) {
+      lk.unlock();
+      flush_graveyard(s->ctx);
+      lk.lock();
+    }
   }
 }
 
 }  // namespace
 
 rid_server* server_create(rid_context* ctx, const rid_server_opts& o) {
+  RID_CHECK(o.max_slots >= 1 && o.max_slots <= 64, RID_ERR_INVALID_ARG, "max_slots must be in [1, 64]");
+  RID_HIP(hipStreamSynchronize(ctx->stream));
   rid_server* s = new rid_server();
   s->ctx = ctx;
   s->opts = o;
   s->epoch = Clock::now();
-  s->worker = std::thread(worker_loop, s);
+  s->defer = new DeferFree(ctx);
+  s->batcher = new Batcher(ctx);
+  for (int w = 0; w < o.max_slots; ++w) s->workers.emplace_back(worker_loop, s);
   return s;
 }
 
@@ -218,6 +333,7 @@ rid_status server_cancel(rid_server* s, uint64_t ticket) {
   auto it = s->all.find(ticket);
   if (it == s->all.end()) return RID_ERR_INVALID_ARG;
   it->second->cancel = true;
+  s->cv_work.notify_all();
   return RID_OK;
 }
 
@@ -228,7 +344,10 @@ void server_destroy(rid_server* s) {
     for (Req* q : s->queue) q->cancel = true;
   }
   s->cv_work.notify_all();
-  if (s->worker.joinable()) s->worker.join();
+  for (std::thread& t : s->workers)
+    if (t.joinable()) t.join();
+  delete s->batcher;
+  delete s->defer;
   for (auto& kv : s->all) delete kv.second;
   delete s;
 }

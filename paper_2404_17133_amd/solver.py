@@ -36,9 +36,9 @@ def _dptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _need_dev(t: torch.Tensor, shape, name):
-    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
-        raise TypeError("%s must be a float64 CUDA tensor" % name)
+def _need_dev(t: torch.Tensor, shape, name, dtypes=(torch.float64,)):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype not in dtypes:
+        raise TypeError("%s must be a CUDA tensor of dtype %s" % (name, " or ".join(str(d) for d in dtypes)))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -129,7 +129,11 @@ def default_opts(precond: str = "ris", precision: str = "fp64", **kw) -> B.rid_s
 
 
 class Problem:
-    """One molecule: orbital energies and borrowed FP64 device tensors."""
+    """One molecule: orbital energies and borrowed device tensors.
+
+    The three-index tensors are float64, or float32 (then only mixed-precision
+    solves run, and the library keeps no FP32 copy of them).
+    """
 
     def __init__(self, ctx: Context, eps_occ, eps_vir, b_ia, b_ij, b_ab, a_x: float,
                  bris_ia=None, bris_ij=None, bris_ab=None, naux_ris_k: int = 0, t_cut: float = 0.0):
@@ -138,15 +142,16 @@ class Problem:
         self.eps_vir = np.ascontiguousarray(np.asarray(eps_vir, dtype=np.float64))
         no, nv = len(self.eps_occ), len(self.eps_vir)
         naux = b_ia.shape[0]
-        _need_dev(b_ia, (naux, no, nv), "b_ia")
-        _need_dev(b_ij, (naux, no, no), "b_ij")
-        _need_dev(b_ab, (naux, nv, nv), "b_ab")
+        fp = (torch.float64, torch.float32)
+        _need_dev(b_ia, (naux, no, nv), "b_ia", fp)
+        _need_dev(b_ij, (naux, no, no), "b_ij", (b_ia.dtype,))
+        _need_dev(b_ab, (naux, nv, nv), "b_ab", (b_ia.dtype,))
         nris = 0
         if bris_ia is not None:
             nris = bris_ia.shape[0]
-            _need_dev(bris_ia, (nris, no, nv), "bris_ia")
-            _need_dev(bris_ij, (nris, no, no), "bris_ij")
-            _need_dev(bris_ab, (nris, nv, nv), "bris_ab")
+            _need_dev(bris_ia, (nris, no, nv), "bris_ia", fp)
+            _need_dev(bris_ij, (nris, no, no), "bris_ij", (bris_ia.dtype,))
+            _need_dev(bris_ab, (nris, nv, nv), "bris_ab", (bris_ia.dtype,))
         self.no, self.nv, self.naux, self.naux_ris = no, nv, naux, nris
         self.n = no * nv
         self._keep = (b_ia, b_ij, b_ab, bris_ia, bris_ij, bris_ab)
@@ -157,10 +162,11 @@ class Problem:
         d.eps_occ_host = _dptr(self.eps_occ)
         d.eps_vir_host = _dptr(self.eps_vir)
         d.b_ia_dev, d.b_ij_dev, d.b_ab_dev = b_ia.data_ptr(), b_ij.data_ptr(), b_ab.data_ptr()
-        d.b_dtype = B.RID_F64
+        d.b_dtype = B.RID_F64 if b_ia.dtype == torch.float64 else B.RID_F32
+        d.bris_dtype = B.RID_F64
         if nris:
             d.bris_ia_dev, d.bris_ij_dev, d.bris_ab_dev = bris_ia.data_ptr(), bris_ij.data_ptr(), bris_ab.data_ptr()
-        d.bris_dtype = B.RID_F64
+            d.bris_dtype = B.RID_F64 if bris_ia.dtype == torch.float64 else B.RID_F32
         h = ctypes.c_void_p()
         ctx.check(B.lib.rid_problem_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
@@ -259,6 +265,13 @@ def make_request(kind: str, opts: B.rid_solve_opts, k: int = 0, mode: str = "tda
         r.omega_host = _dptr(om)
         keep.append(p)
     return r, keep
+
+
+def request_footprint(prob: "Problem", req: B.rid_request) -> int:
+    """Estimated device bytes of a request (what the server admits by)."""
+    b = ctypes.c_uint64()
+    prob.ctx.check(B.lib.rid_request_footprint(prob.handle, ctypes.byref(req), ctypes.byref(b)))
+    return int(b.value)
 
 
 def make_result(req: B.rid_request):

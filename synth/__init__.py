@@ -17,4 +17,5 @@ from .generate import (  # noqa: F401
     make_dipoles,
     make_block,
     config_sizes,
+    molecule_sizes,
 )

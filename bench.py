@@ -105,6 +105,184 @@ def measured_traffic(family: str, dtype: str):
     return None
 
 
+def f32_problem(rid, ctx, d, dipoles=False):
+    """A synthetic molecule generated in FP64 on the device and lent to the
+    library as FP32 tensors (the FP64 copy is freed; only mixed-precision
+    solves run on it).  Returns (problem, dipole block or None)."""
+    import torch
+
+    from synth import make_dipoles, make_problem
+
+    p = make_problem(d["no"], d["nv"], d["naux"], d["naux_ris"], naux_ris_k=d["naux_ris_k"], seed=d["seed"],
+                     device="cuda:0")
+    dip = make_dipoles(p, 3) if dipoles else None
+    t = [x.float() for x in (p.b_ia, p.b_ij, p.b_ab, p.bris_ia, p.bris_ij, p.bris_ab)]
+    eo, ev = p.eps_occ.cpu().numpy(), p.eps_vir.cpu().numpy()
+    a_x, nk, tc = p.a_x, p.naux_ris_k, p.t_cut
+    del p
+    torch.cuda.empty_cache()
+    return rid.Problem(ctx, eo, ev, t[0], t[1], t[2], a_x, t[3], t[4], t[5], nk, tc), dip
+
+
+def bench_batch(args):
+    """Batched workload: molecules m = 0..M-1 of synth.batch_member (no
+    log-uniform in [20, 200], RPA eigen-solves with k in {5, 10, 20}), mixed
+    precision, rid preconditioner, solved together by rid_batch_solve."""
+    import numpy as np
+    import torch
+
+    import paper_2404_17133_amd as rid
+    from synth import batch_member
+
+    members = [batch_member(m) for m in range(args.molecules)]
+    ctx = rid.Context(0)
+    t0 = time.time()
+    probs = [None] * len(members)
+    for m in sorted(range(len(members)), key=lambda i: -members[i]["no"]):
+        probs[m], _ = f32_problem(rid, ctx, members[m])
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    log("%d molecules generated in %.1f s (FP32 tensors %.1f GB; device memory free %.1f of %.1f GB)"
+        % (len(members), time.time() - t0, sum(p._keep[0].numel() + p._keep[1].numel() + p._keep[2].numel()
+                                               for p in probs) * 4e-9, free / 1e9, total / 1e9))
+    opts = rid.default_opts("ris", "mixed")
+    reqs = [rid.make_request("eigen", opts, k=d["k"], mode="rpa")[0] for d in members]
+    roots = sum(d["k"] for d in members)
+
+    def run():
+        ts = time.perf_counter()
+        st, out = rid.batch_solve(ctx, probs, reqs)
+        el = time.perf_counter() - ts
+        if st != 0:
+            raise RuntimeError("batch status %d: %s; %s" % (st, [o["status"] for o in out], ctx.last_error()))
+        return el, out
+
+    for w in range(args.warmup):
+        el, _ = run()
+        log("warmup batch %d: %.2f s" % (w, el))
+    ctx.profile(True)
+    ctx.profile_read()
+    lats, last, total = [], None, 0.0
+    for s in range(args.steps):
+        el, last = run()
+        total += el
+        lats += [o["t_done_ms"] * 1e-3 for o in last]
+        log("batch %d: %.2f s" % (s, el))
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    value = roots * args.steps / total
+    out = {
+        "metric": "converged roots/sec + p50/p99 solve latency, mixed-precision vs FP64 Davidson",
+        "value": round(value, 4), "unit": "roots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / args.steps, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch of %d molecules, no log-uniform in [20, 200], nv=4no, Naux=20no, "
+                               "Naux_ris=4.5no, full-TDDFT k in {5,10,20}, rid preconditioner, mixed precision, "
+                               "one rid_batch_solve per step" % len(members), "roots_per_step": roots},
+        "latency_s": {"p50": round(float(np.percentile(lats, 50)), 3),
+                      "p99": round(float(np.percentile(lats, 99)), 3)},
+        "kernels": {kf: {"launches": v["launches"], "ms": round(v["ms"], 1),
+                         "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 1)}
+                    for kf, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:8]},
+        "iterations": {"mean": float(np.mean([o["stats"]["n_iter"] for o in last])),
+                       "max": int(max(o["stats"]["n_iter"] for o in last))},
+        "members": [[d["no"], d["k"], o["stats"]["n_iter"], o["stats"]["n_mv"], round(o["t_start_ms"] * 1e-3, 2),
+                     round(o["t_done_ms"] * 1e-3, 2)] for d, o in zip(members, last)],
+    }
+    if args.sequential:
+        ts = time.perf_counter()
+        for p, r in zip(probs, reqs):
+            st, o = rid.batch_solve(ctx, [p], [r])
+            if st != 0:
+                raise RuntimeError("sequential status %d" % st)
+        seq = time.perf_counter() - ts
+        out["sequential"] = {"value": round(roots / seq, 4), "unit": "roots/s", "seconds": round(seq, 2),
+                             "speedup_batched_vs_sequential": round(value / (roots / seq), 3)}
+        log("sequential: %.2f s" % seq)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Served stream: requests of synth.serve_trace (no log-uniform in
+    [20, no_max], 70% TDA/RPA eigen k 5..20, 30% polarizability 3 RHS x 3
+    frequencies), mixed precision, rid preconditioner.  First all requests
+    arrive at once (saturated throughput), then the same requests arrive as a
+    Poisson stream at `load` times that throughput (latency percentiles)."""
+    import numpy as np
+    import torch
+
+    import paper_2404_17133_amd as rid
+    from synth import serve_trace
+
+    trace = serve_trace(args.requests, no_max=args.no_max)
+    ctx = rid.Context(0)
+    t0 = time.time()
+    probs, dips = [None] * len(trace), [None] * len(trace)
+    for r in sorted(range(len(trace)), key=lambda i: -trace[i]["no"]):
+        probs[r], dips[r] = f32_problem(rid, ctx, trace[r], dipoles=trace[r]["kind"] != "eigen")
+    torch.cuda.synchronize()
+    log("%d requests' molecules generated in %.1f s" % (len(trace), time.time() - t0))
+    opts = rid.default_opts("ris", "mixed")
+    reqs, keeps, roots = [], [], 0
+    for d, dp in zip(trace, dips):
+        if d["kind"] == "eigen":
+            r, kp = rid.make_request("eigen", opts, k=d["k"], mode=d["mode"])
+            roots += d["k"]
+        else:
+            r, kp = rid.make_request("polarizability", opts, p=dp, omegas=d["omegas"])
+            roots += 3 * len(d["omegas"])
+        reqs.append(r)
+        keeps.append(kp)
+
+    def serve(gaps):
+        srv = rid.Server(ctx, hbm_budget_bytes=args.hbm_budget_gb << 30, max_slots=args.slots)
+        tick = []
+        ts = time.perf_counter()
+        tnext = ts
+        for i, (p, r) in enumerate(zip(probs, reqs)):
+            tnext += gaps[i]
+            delay = tnext - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tick.append(srv.submit(p, r, keep=keeps[i]))
+        res = [srv.wait(t) for t in tick]
+        srv.close()
+        bad = [x["status"] for x in res if x["status"] != 0]
+        if bad:
+            raise RuntimeError("served requests failed: %s" % bad)
+        lat = np.array([(x["t_done_ms"] - x["t_arrival_ms"]) * 1e-3 for x in res])
+        span = (max(x["t_done_ms"] for x in res) - min(x["t_arrival_ms"] for x in res)) * 1e-3
+        return lat, span
+
+    lat_s, span_s = serve([0.0] * len(trace))
+    rate = len(trace) / span_s
+    log("saturated: %.2f s for %d requests (%.3f req/s)" % (span_s, len(trace), rate))
+    gaps = [d["gap"] / (args.load * rate) for d in trace]
+    lat_p, span_p = serve(gaps)
+    log("Poisson at %.2f x saturation: %.2f s" % (args.load, span_p))
+    out = {
+        "metric": "converged roots/sec + p50/p99 solve latency, mixed-precision vs FP64 Davidson",
+        "value": round(roots / span_s, 4), "unit": "roots/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * span_s, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "served stream of %d requests, no log-uniform in [20, %d], 70%% TDA/RPA eigen "
+                               "k 5..20, 30%% polarizability 3 RHS x 3 frequencies, rid preconditioner, mixed "
+                               "precision, %d slots" % (len(trace), args.no_max, args.slots),
+                   "roots_per_pass": roots},
+        "latency_s": {"p50": round(float(np.percentile(lat_p, 50)), 3),
+                      "p99": round(float(np.percentile(lat_p, 99)), 3),
+                      "arrivals": "Poisson at %.2f x the saturated request rate (%.4f req/s)"
+                                  % (args.load, args.load * rate)},
+        "poisson_roots_per_s": round(roots / span_p, 4),
+        "saturated_latency_s": {"p50": round(float(np.percentile(lat_s, 50)), 3),
+                                "p99": round(float(np.percentile(lat_s, 99)), 3)},
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,10 +295,28 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy (x * 1.0 on float32) run before timing, so that "
                          "hardware-counter runs can calibrate byte counters against a known size")
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve"],
+                    help="single: one no=200 molecule (default); batch: many molecules in one batched "
+                         "solve; serve: a request stream through the server")
+    ap.add_argument("--molecules", type=int, default=64, help="batch: number of molecules")
+    ap.add_argument("--sequential", action="store_true", help="batch: also solve the molecules one by one")
+    ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
+    ap.add_argument("--no-max", type=int, default=300, help="serve: largest number of occupied orbitals")
+    ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturated rate")
+    ap.add_argument("--slots", type=int, default=8, help="serve: concurrent requests")
+    ap.add_argument("--hbm-budget-gb", type=int, default=96, help="serve: admission budget")
     args = ap.parse_args()
+    if args.workload != "single":
+        # many concurrent solve streams: more hardware queues keep them from
+        # queueing behind each other (set before the HIP runtime starts)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

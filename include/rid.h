@@ -243,7 +243,9 @@ RID_API rid_status rid_profile_read(rid_context* ctx, rid_kernel_stat* out, int3
  * A request is an eigen-solve (kind 0: k, mode) or a polarizability solve
  * (kind 1: nrhs, p_dev, nfreq, omega_host).  Results are written into the
  * caller-owned rid_result of each request.  rid_batch_solve runs up to 16
- * solves at once, each on a stream of its own; the operator products of all
+ * solves at once (largest first, while their estimated footprints fit 80% of
+ * the device memory free at the call), each on a stream of its own; the
+ * operator products of all
  * solves waiting at the same time go out together, one persistent grouped
  * GEMM launch per contraction stage and tile shape.  Each result equals
  * that of the same request solved alone.  Returns the worst status. */
@@ -262,15 +264,18 @@ typedef struct {
   double* alpha_host;      /* caller buffer: nfreq*nrhs*nrhs (polarizability) */
   double* resid_host;      /* caller buffer or NULL */
   rid_stats stats;
-  double t_arrival_ms, t_admit_ms, t_done_ms; /* server timestamps */
+  double t_arrival_ms, t_admit_ms, t_done_ms; /* server timestamps; rid_batch_solve: 0, start, end of
+                                                 the request from the start of the batch */
 } rid_result;
 
 RID_API rid_status rid_batch_solve(rid_context* ctx, int32_t n, rid_problem* const* probs,
                            const rid_request* reqs, rid_result* results);
 
-/* Estimated device bytes a request needs beyond its problem's borrowed
- * tensors (subspace, products, inner-solve blocks, scratch, FP32 copies of
- * FP64 tensors for a mixed-precision solve); the server admits by it. */
+/* Estimated device bytes a request needs while it runs (subspace, products,
+ * inner-solve blocks, operator scratch); the server and rid_batch_solve
+ * admit by it.  The problem's own tensor copies (FP32 casts and transposes,
+ * BF16 ris copies) are made when a request is submitted or a batch starts,
+ * and count in rid_problem_footprint instead. */
 RID_API rid_status rid_request_footprint(const rid_problem* prob, const rid_request* req, uint64_t* bytes);
 
 /* ---- continuous-batching server -----------------------------------------

@@ -144,9 +144,9 @@ def davidson_rpa(apply_pm: Callable, de: np.ndarray, k: int, v0: np.ndarray,
             lo = np.linalg.cholesky(am)
         except np.linalg.LinAlgError as e:
             raise IndefiniteError("projected A-B is not positive definite") from e
-        w2, wv = np.linalg.eigh(_sym(lo.T @ ap @ lo))
-        kk = min(k, len(w2))
-        w2, wv = w2[:kk], wv[:, :kk]
+        w2all, wvall = np.linalg.eigh(_sym(lo.T @ ap @ lo))
+        kk = min(k, len(w2all))
+        w2, wv = w2all[:kk], wvall[:, :kk]
         if np.any(w2 <= 0.0):
             raise IndefiniteError("non-positive Omega^2 in the projected problem")
         om = np.sqrt(w2)
@@ -166,7 +166,14 @@ def davidson_rpa(apply_pm: Callable, de: np.ndarray, k: int, v0: np.ndarray,
         new, ninner = precond(rz[:, act], rzp[:, act], om[act])
         n_inner += ninner
         if v.shape[1] + new.shape[1] > m_max:
-            c = orthonormalize(np.hstack([z[:, :keep], zp[:, :keep]]))
+            # restart on the Z and Z' of the `keep` lowest positive Ritz pairs
+            nk = int(min(max(keep, kk), len(w2all)))
+            while nk > kk and w2all[nk - 1] <= 0.0:
+                nk -= 1
+            omk = np.sqrt(w2all[:nk])
+            zk = (lo @ wvall[:, :nk]) / np.sqrt(omk)[None, :]
+            zpk = (ap @ zk) / omk[None, :]
+            c = orthonormalize(np.hstack([zk, zpk]))
             v, pv, mv = v @ c, pv @ c, mv @ c
         vn = orthonormalize(new, v)
         if vn.shape[1] == 0:

@@ -119,18 +119,44 @@ void dev_free(rid_context* ctx, void* p) {
   }
 }
 
+namespace {
+thread_local hipStream_t tl_stream = nullptr;
+}  // namespace
+
+hipStream_t thread_stream() { return tl_stream; }
+ThreadStream::ThreadStream(hipStream_t s) : prev(tl_stream) { tl_stream = s; }
+ThreadStream::~ThreadStream() { tl_stream = prev; }
+
 void DevBuf::release() {
   if (p && ctx) {
     bool park = false;
     {
       std::lock_guard<std::mutex> g(ctx->grave_mu);
-      if (ctx->defer_free > 0) {
-        ctx->graveyard.push_back(p);
-        ctx->grave_bytes += bytes;
-        park = true;
-      }
+      park = ctx->defer_free > 0;
     }
-    if (!park) {
+    if (park) {
+      hipEvent_t ev = nullptr;
+      {
+        std::lock_guard<std::mutex> g(ctx->grave_mu);
+        if (!ctx->grave_events.empty()) {
+          ev = ctx->grave_events.back();
+          ctx->grave_events.pop_back();
+        }
+      }
+      if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+      hipStream_t s = tl_stream ? tl_stream : ctx->stream;
+      if (ev && hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        ev = nullptr;
+      }
+      if (!ev) (void)hipDeviceSynchronize();  // no fence available: wait for everything
+      {
+        std::lock_guard<std::mutex> g(ctx->grave_mu);
+        ctx->graveyard.push_back(rid_context::Parked{p, bytes, ev});
+        ctx->grave_bytes += bytes;
+      }
+      reap_graveyard(ctx, false);
+    } else {
       // memory may still be in use by queued work on the context stream
       (void)hipStreamSynchronize(ctx->stream);
       dev_free(ctx, p);
@@ -140,16 +166,38 @@ void DevBuf::release() {
   bytes = 0;
 }
 
-void flush_graveyard(rid_context* ctx) {
-  std::vector<void*> v;
+void reap_graveyard(rid_context* ctx, bool wait) {
+  std::vector<rid_context::Parked> done;
   {
     std::lock_guard<std::mutex> g(ctx->grave_mu);
-    v.swap(ctx->graveyard);
-    ctx->grave_bytes = 0;
+    std::vector<rid_context::Parked> keep;
+    for (const rid_context::Parked& q : ctx->graveyard) {
+      bool ready = !q.ev;
+      if (!ready) {
+        if (wait) {
+          (void)hipEventSynchronize(q.ev);
+          ready = true;
+        } else {
+          const hipError_t e = hipEventQuery(q.ev);
+          ready = e == hipSuccess;
+          if (e != hipSuccess && e != hipErrorNotReady) {
+            (void)hipGetLastError();
+            (void)hipEventSynchronize(q.ev);
+            ready = true;
+          }
+        }
+      }
+      if (ready) {
+        done.push_back(q);
+        ctx->grave_bytes -= q.bytes;
+        if (q.ev) ctx->grave_events.push_back(q.ev);
+      } else {
+        keep.push_back(q);
+      }
+    }
+    ctx->graveyard.swap(keep);
   }
-  if (v.empty()) return;
-  (void)hipDeviceSynchronize();
-  for (void* q : v) dev_free(ctx, q);
+  for (const rid_context::Parked& q : done) dev_free(ctx, q.p);
 }
 
 DeferFree::DeferFree(rid_context* c) : ctx(c) {
@@ -771,6 +819,17 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
 
 }  // namespace
 
+void prepare_problem(rid_problem* P, const rid_solve_opts& o) {
+  const bool mixed = o.precision == RID_PRECISION_MIXED;
+  const bool ris = o.precond == RID_PRECOND_RIS && P->has_ris();
+  if (mixed) {
+    P->ensure_f32();
+    if (ris) P->ensure_bf16();
+  } else {
+    if (P->b_dt == RID_F64) P->ensure_f64_aux();
+  }
+}
+
 void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st) {
   for (int prec = PREC_F64; prec <= PREC_BF16; ++prec)
     for (int r = 0; r < 2; ++r) {
@@ -810,10 +869,12 @@ void apply_operator(rid_problem* P, int kind, int prec, int nvec, const double* 
 
 Batcher::Batcher(rid_context* ctx) : ctx_(ctx) {
   RID_HIP(hipSetDevice(ctx->device));
-  RID_HIP(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
-  events_.resize(64, nullptr);
-  for (hipEvent_t& e : events_) RID_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  thread_ = std::thread([this] { loop(); });
+  for (Lane& L : lanes_) {
+    RID_HIP(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking));
+    L.events.resize(64, nullptr);
+    for (hipEvent_t& e : L.events) RID_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  for (Lane& L : lanes_) L.thread = std::thread([this, &L] { loop(L); });
 }
 
 Batcher::~Batcher() {
@@ -821,12 +882,14 @@ Batcher::~Batcher() {
     std::lock_guard<std::mutex> g(mu_);
     stop_ = true;
   }
-  cv_.notify_all();
-  if (thread_.joinable()) thread_.join();
-  (void)hipStreamSynchronize(st_);
-  for (hipEvent_t e : events_)
-    if (e) (void)hipEventDestroy(e);
-  (void)hipStreamDestroy(st_);
+  for (Lane& L : lanes_) L.cv.notify_all();
+  for (Lane& L : lanes_) {
+    if (L.thread.joinable()) L.thread.join();
+    (void)hipStreamSynchronize(L.st);
+    for (hipEvent_t e : L.events)
+      if (e) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(L.st);
+  }
 }
 
 void Batcher::apply(OpJob& j) {
@@ -834,33 +897,35 @@ void Batcher::apply(OpJob& j) {
   j.code = 0;
   j.msg.clear();
   RID_HIP(hipEventRecord(j.ready, j.stream));
+  Lane& L = lanes_[(j.kind == OPK_T || j.kind == OPK_TPAIR) ? 1 : 0];
   std::unique_lock<std::mutex> lk(mu_);
-  pending_.push_back(&j);
-  cv_.notify_all();
+  L.pending.push_back(&j);
+  L.cv.notify_all();
   cv_done_.wait(lk, [&] { return j.finished; });
   if (j.code != 0) throw Error((rid_status)j.code, j.msg);
 }
 
-void Batcher::loop() {
+void Batcher::loop(Lane& L) {
   (void)hipSetDevice(ctx_->device);
+  ThreadStream ts(L.st);
   std::unique_lock<std::mutex> lk(mu_);
   while (true) {
-    cv_.wait(lk, [&] { return stop_ || !pending_.empty(); });
-    if (pending_.empty()) {
+    L.cv.wait(lk, [&] { return stop_ || !L.pending.empty(); });
+    if (L.pending.empty()) {
       if (stop_) return;
       continue;
     }
     std::vector<OpJob*> batch;
-    batch.swap(pending_);
+    batch.swap(L.pending);
     lk.unlock();
     int code = 0;
     std::string msg;
     try {
-      for (OpJob* j : batch) RID_HIP(hipStreamWaitEvent(st_, j->ready, 0));
-      run_jobs(ctx_, batch.data(), (int)batch.size(), st_);
-      hipEvent_t done = events_[next_event_];
-      next_event_ = (next_event_ + 1) % (int)events_.size();
-      RID_HIP(hipEventRecord(done, st_));
+      for (OpJob* j : batch) RID_HIP(hipStreamWaitEvent(L.st, j->ready, 0));
+      run_jobs(ctx_, batch.data(), (int)batch.size(), L.st);
+      hipEvent_t done = L.events[L.next_event];
+      L.next_event = (L.next_event + 1) % (int)L.events.size();
+      RID_HIP(hipEventRecord(done, L.st));
       for (OpJob* j : batch) RID_HIP(hipStreamWaitEvent(j->stream, done, 0));
     } catch (const Error& e) {
       code = e.code;
@@ -870,8 +935,8 @@ void Batcher::loop() {
       msg = e.what();
     }
     lk.lock();
-    rounds_ += 1;
-    jobs_ += (int64_t)batch.size();
+    L.rounds += 1;
+    L.jobs += (int64_t)batch.size();
     for (OpJob* j : batch) {
       j->code = code;
       j->msg = msg;
@@ -959,4 +1024,5 @@ rid_context::~rid_context() {
   delete ring;
   ring = nullptr;
   rid::flush_graveyard(this);
+  for (hipEvent_t e : grave_events) (void)hipEventDestroy(e);
 }

@@ -71,12 +71,19 @@ struct rid_context {
   rid::Profiler prof;
   std::mutex tune_mu;
   std::map<rid::TuneKey, rid::TuneVal> tune;
-  // While solves run on several streams (batched solves, the server), freed
-  // device buffers are parked here and released after a device-wide
-  // synchronisation, since the stream that last used them is not known.
+  // While solves run on several streams (batched solves, the server), a
+  // freed device buffer is parked with an event recorded on the releasing
+  // thread's stream, and handed back to the allocator once that event has
+  // completed (every earlier use of the buffer is ordered before it).
+  struct Parked {
+    void* p;
+    size_t bytes;
+    hipEvent_t ev;
+  };
   int defer_free = 0;  // nesting count, guarded by grave_mu
   std::mutex grave_mu;
-  std::vector<void*> graveyard;
+  std::vector<Parked> graveyard;
+  std::vector<hipEvent_t> grave_events;  // recycled
   uint64_t grave_bytes = 0;
   rid::DescRing* ring = nullptr;  // grouped-GEMM descriptor staging
   ~rid_context();
@@ -101,8 +108,18 @@ namespace rid {
 
 void* dev_alloc(rid_context* ctx, size_t bytes);
 void dev_free(rid_context* ctx, void* p);
-// Release parked buffers (synchronises the device when there are any).
-void flush_graveyard(rid_context* ctx);
+// Release parked buffers whose fence events have completed; with wait, wait
+// for all of them first.
+void reap_graveyard(rid_context* ctx, bool wait);
+inline void flush_graveyard(rid_context* ctx) { reap_graveyard(ctx, true); }
+// The stream whose position fences this host thread's buffer releases: a
+// solve's thread sets its stream, a batcher lane thread its lane stream.
+hipStream_t thread_stream();
+struct ThreadStream {
+  hipStream_t prev;
+  explicit ThreadStream(hipStream_t s);
+  ~ThreadStream();
+};
 // Scope in which buffer releases are deferred (see rid_context::graveyard).
 struct DeferFree {
   rid_context* ctx;
@@ -221,32 +238,44 @@ struct OpJob {
 void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st);
 
 // Collects operator products from solves running on several host threads
-// and streams, and runs whatever is waiting as one grouped product on its
-// own stream, from a thread of its own.  apply() returns once the product
-// is enqueued: the caller's stream waits for it with an event.
+// and streams, and runs whatever is waiting as one grouped product on a
+// stream of its own, from a thread of its own.  Two lanes, each with its own
+// thread and stream: the outer products, and the small ris-model products of
+// the inner solves, so that an inner iteration does not wait behind a round
+// of large outer products.  apply() returns once the product is enqueued: the
+// caller's stream waits for it with an event.
 class Batcher {
  public:
   explicit Batcher(rid_context* ctx);
   ~Batcher();
   void apply(OpJob& j);  // throws rid::Error when the product failed
-  int64_t rounds() const { return rounds_; }
-  int64_t jobs() const { return jobs_; }
+  int64_t rounds() const { return lanes_[0].rounds + lanes_[1].rounds; }
+  int64_t jobs() const { return lanes_[0].jobs + lanes_[1].jobs; }
 
  private:
-  void loop();
+  struct Lane {
+    hipStream_t st = nullptr;
+    std::condition_variable cv;
+    std::vector<OpJob*> pending;
+    int64_t rounds = 0, jobs = 0;
+    std::vector<hipEvent_t> events;
+    int next_event = 0;
+    std::thread thread;
+  };
+  void loop(Lane& L);
   rid_context* ctx_;
-  hipStream_t st_ = nullptr;
   std::mutex mu_;
-  std::condition_variable cv_, cv_done_;
-  std::vector<OpJob*> pending_;
+  std::condition_variable cv_done_;
   bool stop_ = false;
-  int64_t rounds_ = 0, jobs_ = 0;
-  std::vector<hipEvent_t> events_;
-  int next_event_ = 0;
-  std::thread thread_;
+  Lane lanes_[2];
 };
 
 // Validate (kind, prec) combinations; throws rid::Error.
 void check_operator(const rid_problem* P, int kind, int prec);
+
+// Build the problem's lazily made tensor copies that solves with options o
+// read (FP32 casts and transposes for the mixed path, BF16 ris copies, FP64
+// transposes), so that their memory is in place before solves are admitted.
+void prepare_problem(rid_problem* P, const rid_solve_opts& o);
 
 }  // namespace rid

@@ -40,6 +40,7 @@ double ms_since(Clock::time_point t0) {
 
 // Per-solve device context: stream, scratch, transfers and operator products.
 struct Eng {
+  ThreadStream fence;  // first member: fences buffer releases until the last member is gone
   rid_problem* P;
   hipStream_t st;
   long N;
@@ -50,7 +51,7 @@ struct Eng {
   OpWork own;     // operator scratch of a solve that shares the device
   hipEvent_t ready = nullptr;
   Eng(rid_problem* p, SolveStats* s, const ExecCfg& ex)
-      : P(p), st(ex.stream ? ex.stream : p->ctx->stream), N(p->n()), part(p->ctx), tmp1(p->ctx), tmp2(p->ctx),
+      : fence(ex.stream ? ex.stream : p->ctx->stream), P(p), st(ex.stream ? ex.stream : p->ctx->stream), N(p->n()), part(p->ctx), tmp1(p->ctx), tmp2(p->ctx),
         ints(p->ctx), dscal(p->ctx), stats(s), batcher(ex.batcher), own(p->ctx) {
     if (batcher) RID_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
   }
@@ -145,20 +146,22 @@ struct Basis {
 
 // Orthonormalise nnew directions W (row-major, ld N; overwritten) against the
 // basis and each other, append the accepted ones.  Returns the number added.
+// Every step runs on the device; direction j is written to basis slot m0 + j
+// (zero when dropped), so that the host reads the norms once, at the end, and
+// then closes the gaps left by dropped directions.
 int append_orthonormal(Eng& E, Basis& B, double* W, int nnew, double drop_tol = 1e-8) {
   if (nnew <= 0) return 0;
   ProfScope ps(E.P->ctx, E.st, "orthonormalize", 0.0, 0.0);
   const long N = E.N;
   RID_CHECK(B.m + nnew <= B.cap, RID_ERR_INTERNAL, "basis capacity exceeded");
-  E.tmp1.ensure(sizeof(double) * (size_t)std::max(B.m, 1) * nnew + 64 * sizeof(double));
-  double* nrm_d = E.tmp1.as<double>();
+  E.tmp1.ensure(sizeof(double) * (size_t)(2 * nnew + 64));
+  double* nrm_d = E.tmp1.as<double>();       // initial norms
+  double* fin_d = nrm_d + nnew;               // norms after orthogonalisation
   {
     RedScratch rs = E.rs(1, nnew);
     col_norms(W, N, nnew, N, nrm_d, rs, E.st);
   }
-  std::vector<double> nrm(nnew);
-  E.d2h(nrm.data(), nrm_d, sizeof(double) * nnew);
-  scale_cols(W, N, nnew, N, nrm_d, 1, E.st);
+  scale_cols(W, N, nnew, N, nrm_d, 1, E.st);  // unit vectors (zero stays zero)
   if (B.m > 0) {
     E.tmp2.ensure(sizeof(double) * (size_t)B.m * nnew);
     double* c = E.tmp2.as<double>();
@@ -172,26 +175,31 @@ int append_orthonormal(Eng& E, Basis& B, double* W, int nnew, double drop_tol = 
   E.tmp2.ensure(sizeof(double) * (size_t)(nnew + 8));
   double* c = E.tmp2.as<double>();
   for (int j = 0; j < nnew; ++j) {
-    if (!std::isfinite(nrm[j]) || nrm[j] == 0.0) continue;
     double* wj = W + (long)j * N;
-    const int acc = B.m - m0;
-    if (acc > 0) {
+    if (j > 0) {
       for (int pass = 0; pass < 2; ++pass) {
-        RedScratch rs = E.rs(acc, 1);
-        gram(B.V(m0), N, acc, wj, N, 1, N, c, 1, rs, E.st);
-        combo(B.V(m0), N, acc, c, 1, 1, 1, N, -1.0, 1.0, wj, N, E.st);
+        RedScratch rs = E.rs(j, 1);
+        gram(B.V(m0), N, j, wj, N, 1, N, c, 1, rs, E.st);
+        combo(B.V(m0), N, j, c, 1, 1, 1, N, -1.0, 1.0, wj, N, E.st);
       }
     }
     {
       RedScratch rs = E.rs(1, 1);
-      col_norms(wj, N, 1, N, c, rs, E.st);
+      col_norms(wj, N, 1, N, fin_d + j, rs, E.st);
     }
-    double r = 0.0;
-    E.d2h(&r, c, sizeof(double));
-    if (!(r >= drop_tol)) continue;
-    scale_copy(wj, N, 1.0 / r, B.V(B.m), E.st);
-    B.m += 1;
+    accept_scale(wj, N, fin_d + j, drop_tol, B.V(m0 + j), E.st);
   }
+  std::vector<double> nrm(2 * nnew);
+  E.d2h(nrm.data(), nrm_d, sizeof(double) * 2 * nnew);
+  int pos = m0;
+  for (int j = 0; j < nnew; ++j) {
+    const bool ok = std::isfinite(nrm[j]) && nrm[j] != 0.0 && nrm[nnew + j] >= drop_tol;
+    if (!ok) continue;
+    if (pos != m0 + j)
+      RID_HIP(hipMemcpyAsync(B.V(pos), B.V(m0 + j), sizeof(double) * N, hipMemcpyDeviceToDevice, E.st));
+    ++pos;
+  }
+  B.m = pos;
   return B.m - m0;
 }
 
@@ -201,7 +209,9 @@ void multiply(Eng& E, Basis& B, int m0, int kind, int prec, double& t_acc) {
   if (nn <= 0) return;
   auto t0 = Clock::now();
   E.apply(kind, prec, nn, B.V(m0), B.P1(m0), B.nprod == 2 ? B.P2(m0) : nullptr);
-  E.sync();
+  // alone, wait for the product so that its time is known; a solve that
+  // shares the device goes on enqueueing (its time then counts submission)
+  if (!E.batcher) E.sync();
   t_acc += ms_since(t0);
 }
 
@@ -691,10 +701,88 @@ void davidson_sym(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
   (void)t_start;
 }
 
+// Restart of the shared (Z, Z') subspace: collapse the basis onto the span of
+// the Z and Z' of the ncol lowest Ritz pairs (coefficient vectors: the
+// columns of zc, zpc of the Ritz step, row stride ld), orthonormalised in the
+// coefficient space.  Exact by linearity:
+// V' = V Q, (A+-B) V' = P Q and a' = Q^T a Q.  The coefficient work is small
+// (m x 2kk) and runs on the host.
+void restart_pair(Eng& E, Basis& B, const Ritz& R, int ld, int ncol) {
+  const int m = B.m;
+  const long N = E.N;
+  std::vector<double> zc((size_t)m * ld), zpc((size_t)m * ld);
+  E.d2h(zc.data(), R.zc.p, sizeof(double) * zc.size());
+  E.d2h(zpc.data(), R.zpc.p, sizeof(double) * zpc.size());
+  std::vector<std::vector<double>> acc;
+  for (int src = 0; src < 2; ++src)
+    for (int j = 0; j < ncol; ++j) {
+      const std::vector<double>& c = src == 0 ? zc : zpc;
+      std::vector<double> v(m);
+      for (int i = 0; i < m; ++i) v[i] = c[(size_t)i * ld + j];
+      double nrm = 0.0;
+      for (double x : v) nrm += x * x;
+      nrm = std::sqrt(nrm);
+      if (!(nrm > 0.0)) continue;
+      for (double& x : v) x /= nrm;
+      for (int pass = 0; pass < 2; ++pass)
+        for (const std::vector<double>& q : acc) {
+          double d = 0.0;
+          for (int i = 0; i < m; ++i) d += q[i] * v[i];
+          for (int i = 0; i < m; ++i) v[i] -= d * q[i];
+        }
+      nrm = 0.0;
+      for (double x : v) nrm += x * x;
+      nrm = std::sqrt(nrm);
+      if (!(nrm >= 1e-8)) continue;
+      for (double& x : v) x /= nrm;
+      acc.push_back(std::move(v));
+    }
+  const int r = (int)acc.size();
+  RID_CHECK(r > 0, RID_ERR_BREAKDOWN, "restart subspace is empty");
+  std::vector<double> q((size_t)m * r);
+  for (int c = 0; c < r; ++c)
+    for (int i = 0; i < m; ++i) q[(size_t)i * r + c] = acc[c][i];
+  // a' = Q^T a Q for both projected matrices
+  for (int t = 0; t < 2; ++t) {
+    DevBuf& ad = t == 0 ? B.a1 : B.a2;
+    std::vector<double> a((size_t)B.cap * B.cap);
+    E.d2h(a.data(), ad.p, sizeof(double) * a.size());
+    std::vector<double> aq((size_t)m * r, 0.0), an((size_t)B.cap * B.cap, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int l = 0; l < m; ++l) {
+        const double ail = a[(size_t)i * B.cap + l];
+        for (int c = 0; c < r; ++c) aq[(size_t)i * r + c] += ail * q[(size_t)l * r + c];
+      }
+    for (int c = 0; c < r; ++c)
+      for (int d = 0; d < r; ++d) {
+        double v = 0.0;
+        for (int i = 0; i < m; ++i) v += q[(size_t)i * r + c] * aq[(size_t)i * r + d];
+        an[(size_t)c * B.cap + d] = v;
+      }
+    for (int c = 0; c < r; ++c)
+      for (int d = 0; d < c; ++d) {
+        const double v = 0.5 * (an[(size_t)c * B.cap + d] + an[(size_t)d * B.cap + c]);
+        an[(size_t)c * B.cap + d] = an[(size_t)d * B.cap + c] = v;
+      }
+    E.h2d(ad.p, an.data(), sizeof(double) * an.size());
+  }
+  DevBuf qd(E.P->ctx), tmp(E.P->ctx);
+  qd.ensure(sizeof(double) * q.size());
+  E.h2d(qd.p, q.data(), sizeof(double) * q.size());
+  tmp.ensure(sizeof(double) * (size_t)r * N);
+  for (int t = 0; t < 3; ++t) {
+    double* base = t == 0 ? B.V(0) : (t == 1 ? B.P1(0) : B.P2(0));
+    combo(base, N, m, qd.as<double>(), r, 1, r, N, 1.0, 0.0, tmp.as<double>(), N, E.st);
+    RID_HIP(hipMemcpyAsync(base, tmp.p, sizeof(double) * (size_t)r * N, hipMemcpyDeviceToDevice, E.st));
+  }
+  E.sync();
+  B.m = r;
+}
+
 // Full-TDDFT Davidson on the pair operator `kind` (OPK_PAIR or OPK_TPAIR).
 // On return zout / zpout (k x N) hold Z = X+Y and Z' = X-Y.
 void davidson_rpa(Eng& E, int kind, int prec, int k, const double* v0, int n0, const PrecondFn& pc, double tol,
-                  int max_iter, int m_max, double* zout, double* zpout, EigCore& core, bool timed) {
+                  int max_iter, int m_max, int keep, double* zout, double* zpout, EigCore& core, bool timed) {
   rid_context* ctx = E.P->ctx;
   const long N = E.N;
   SolveStats& st = *E.stats;
@@ -722,19 +810,23 @@ void davidson_rpa(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
     const int m = B.m;
     const int kk = std::min(kk0, m);
     auto t0 = Clock::now();
+    // the lowest kk pairs are the answer; up to `keep` pairs seed a restart
+    const int nq = std::min(m, std::max(kk, keep));
     std::vector<double> w2;
     int info = 0;
-    ritz_rpa(E, R, B, kk, w2, info);
+    ritz_rpa(E, R, B, nq, w2, info);
     if (info != 0) throw Error(RID_ERR_INDEFINITE, "projected A-B is not positive definite");
-    for (double x : w2)
-      if (!(x > 0.0)) throw Error(RID_ERR_INDEFINITE, "non-positive Omega^2 in the projected problem");
+    for (int j = 0; j < kk; ++j)
+      if (!(w2[j] > 0.0)) throw Error(RID_ERR_INDEFINITE, "non-positive Omega^2 in the projected problem");
+    int nkeep = kk;
+    while (nkeep < nq && w2[nkeep] > 0.0) ++nkeep;
     core.omega.resize(kk);
     for (int j = 0; j < kk; ++j) core.omega[j] = std::sqrt(w2[j]);
     const double* om = R.om.as<double>();
-    combo(B.V(0), N, m, R.zc.as<double>(), kk, 1, kk, N, 1.0, 0.0, zout, N, E.st);
-    combo(B.V(0), N, m, R.zpc.as<double>(), kk, 1, kk, N, 1.0, 0.0, zpout, N, E.st);
-    combo(B.P1(0), N, m, R.zc.as<double>(), kk, 1, kk, N, 1.0, 0.0, pz.as<double>(), N, E.st);
-    combo(B.P2(0), N, m, R.zpc.as<double>(), kk, 1, kk, N, 1.0, 0.0, mz.as<double>(), N, E.st);
+    combo(B.V(0), N, m, R.zc.as<double>(), nq, 1, kk, N, 1.0, 0.0, zout, N, E.st);
+    combo(B.V(0), N, m, R.zpc.as<double>(), nq, 1, kk, N, 1.0, 0.0, zpout, N, E.st);
+    combo(B.P1(0), N, m, R.zc.as<double>(), nq, 1, kk, N, 1.0, 0.0, pz.as<double>(), N, E.st);
+    combo(B.P2(0), N, m, R.zpc.as<double>(), nq, 1, kk, N, 1.0, 0.0, mz.as<double>(), N, E.st);
     residual_pair(pz.as<double>(), zpout, mz.as<double>(), zout, N, kk, N, om, r1.as<double>(), r2.as<double>(),
                   E.st);
     {
@@ -764,11 +856,9 @@ void davidson_rpa(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
     auto tp = Clock::now();
     const int nnew = pc(r1.as<double>(), r2.as<double>(), act, sh, wn.as<double>(), core);
     if (timed) st.t_precond += ms_since(tp);
-    if (B.m + nnew > B.cap) {
-      core.status = RID_WARN_NOT_CONVERGED;
-      break;
-    }
     t0 = Clock::now();
+    if (B.m + nnew > m_max) restart_pair(E, B, R, nq, nkeep);
+    RID_CHECK(B.m + nnew <= B.cap, RID_ERR_INTERNAL, "basis capacity exceeded after restart");
     const int m0 = B.m;
     const int added = append_orthonormal(E, B, wn.as<double>(), nnew);
     if (timed) st.t_other += ms_since(t0);
@@ -882,7 +972,8 @@ rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode,
         return 2 * na;
       };
       davidson_rpa(E, OPK_TPAIR, pin, n_init, u.as<double>(), nt, dpc, o.init_tol, o.init_max_iter,
-                   std::max(200, 40 * n_init), v0.as<double>(), v0.as<double>() + (long)n_init * N, g, false);
+                   std::max(200, 40 * n_init), n_init, v0.as<double>(), v0.as<double>() + (long)n_init * N, g,
+                   false);
       st.n_inner_mv += g.n_mv;
       st.n_inner_iter += g.n_iter;
       n0 = 2 * n_init;
@@ -947,8 +1038,8 @@ rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode,
                  core, true);
   } else {
     zpbuf.ensure(sizeof(double) * k * N);
-    davidson_rpa(E, OPK_PAIR, pout, k, v0.as<double>(), n0, pc, o.tol, o.max_iter, m_max, zbuf.as<double>(),
-                 zpbuf.as<double>(), core, true);
+    davidson_rpa(E, OPK_PAIR, pout, k, v0.as<double>(), n0, pc, o.tol, o.max_iter, m_max, n_init,
+                 zbuf.as<double>(), zpbuf.as<double>(), core, true);
   }
   if (core.status == RID_ERR_BREAKDOWN) throw Error(RID_ERR_BREAKDOWN, "every new direction was dropped");
   st.n_iter = core.n_iter;

@@ -29,18 +29,27 @@ int gram_chunks(int m, int n, long N) {
   return (int)std::max<long>(1, std::min<long>(ch, 4096));
 }
 
-__device__ inline void fold64(double (&a)[64], int lane) {
+// One halving step of the butterfly: 2*O live accumulators become O.  The
+// step width is a template constant so that every array index is known at
+// compile time and the accumulators stay in registers.
+template <int O>
+__device__ inline void fold_step(double (&a)[64], int lane) {
+  const bool upper = (lane & O) != 0;
 #pragma unroll
-  for (int o = 32, cnt = 64; o >= 1; o >>= 1, cnt >>= 1) {
-    const int half = cnt >> 1;
-    const bool upper = (lane & o) != 0;
-#pragma unroll
-    for (int q = 0; q < half; ++q) {
-      const double send = upper ? a[q] : a[q + half];
-      const double keep = upper ? a[q + half] : a[q];
-      a[q] = keep + __shfl_xor(send, o, 64);
-    }
+  for (int q = 0; q < O; ++q) {
+    const double send = upper ? a[q] : a[q + O];
+    const double keep = upper ? a[q + O] : a[q];
+    a[q] = keep + __shfl_xor(send, O, 64);
   }
+}
+
+__device__ inline void fold64(double (&a)[64], int lane) {
+  fold_step<32>(a, lane);
+  fold_step<16>(a, lane);
+  fold_step<8>(a, lane);
+  fold_step<4>(a, lane);
+  fold_step<2>(a, lane);
+  fold_step<1>(a, lane);
 }
 
 __global__ __launch_bounds__(256) void gram_part_kernel(const double* __restrict__ V, long ldv, int m,
@@ -272,7 +281,23 @@ __global__ void scale_copy_kernel(const double* __restrict__ src, long n, double
     dst[t] = alpha * src[t];
 }
 
+// dst = src / r when r = *rp >= tol, else dst = 0 (a dropped direction).
+__global__ void accept_scale_kernel(const double* __restrict__ src, long n, const double* __restrict__ rp, double tol,
+                                    double* __restrict__ dst) {
+  const double r = *rp;
+  const bool ok = r >= tol;
+  const double alpha = ok ? 1.0 / r : 0.0;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    dst[t] = ok ? alpha * src[t] : 0.0;
+}
+
 }  // namespace
+
+void accept_scale(const double* src, long n, const double* r, double tol, double* dst, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(accept_scale_kernel, dim3(grid1(n)), dim3(256), 0, s, src, n, r, tol, dst);
+  RID_HIP(hipGetLastError());
+}
 
 size_t gram_part_elems(int m, int n, long N) { return (size_t)gram_chunks(m, n, N) * std::max(m, 1) * std::max(n, 1); }
 

@@ -55,6 +55,8 @@ void gather_cols(const double* src, long lds, const int* idx, int n, long N, dou
 void unit_vectors(const int* pos, int n, long N, double* out, long ldo, hipStream_t s);
 // Elementwise cast f64 -> f64 negation helper: dst = alpha * src.
 void scale_copy(const double* src, long n, double alpha, double* dst, hipStream_t s);
+// dst = src / r if the device scalar r >= tol, else 0.
+void accept_scale(const double* src, long n, const double* r, double tol, double* dst, hipStream_t s);
 
 // ---- small dense FP64 (dense.hip) -------------------------------------------
 // Symmetric eigen-decomposition of a (m x m, leading dim lda) by cyclic

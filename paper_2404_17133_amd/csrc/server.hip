@@ -36,10 +36,6 @@ typedef std::chrono::steady_clock Clock;
 
 enum ReqState { RQ_QUEUED = 0, RQ_RUNNING = 1, RQ_DONE = 2 };
 
-// Parked device memory above which a finishing solve releases it (this
-// synchronises the device once).
-constexpr uint64_t kFlushBytes = 4ull << 30;
-
 std::mutex g_err_mu;  // last_error is written from several threads
 
 struct Req {
@@ -146,12 +142,14 @@ uint64_t request_footprint(const rid_problem* P, const rid_request& r) {
   const int mm = r.opts.m_max > 0 ? r.opts.m_max : std::max(200, 40 * k);
   const uint64_t basis = (uint64_t)(mm + 4 * k + 8) * N * 8 * 3;  // V and two product blocks
   const uint64_t inner = (uint64_t)(2 * k * (r.opts.inner_max_iter + 1)) * N * 8 * 3;
-  // FP32 copies of FP64 tensors (none when the caller lends FP32 tensors)
-  const uint64_t tens = (P->b_dt == RID_F64 && r.opts.precision == RID_PRECISION_MIXED)
-                            ? (uint64_t)P->naux * (N + (uint64_t)P->no * P->no + (uint64_t)P->nv * P->nv) * 4
-                            : 0;
-  const uint64_t work = (uint64_t)(3 * k) * N * 8 * 6 + (256ull << 20);
-  return basis + inner + tens + work;
+  // vector blocks of the solve, plus the operator scratch: exchange
+  // intermediates (chunked to 256 MB each) and split partial sums (up to 8
+  // splits of a (no * 2k) x nv block, two of them)
+  const uint64_t part = (uint64_t)8 * P->no * (2 * k) * P->nv * 4 * 2;
+  const uint64_t work = (uint64_t)(3 * k) * N * 8 * 6 + (768ull << 20) + part;
+  // the problem's tensor copies are made before admission and charged to
+  // the problem (rid_problem_footprint), not to its requests
+  return basis + inner + work;
 }
 
 rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const rid_request* reqs,
@@ -162,6 +160,7 @@ rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const r
     RID_CHECK(reqs[i].kind == 0 || reqs[i].kind == 1, RID_ERR_INVALID_ARG, "bad request kind");
     results[i].status = RID_ERR_PENDING;
   }
+  for (int i = 0; i < n; ++i) prepare_problem(probs[i], reqs[i].opts);
   RID_HIP(hipStreamSynchronize(ctx->stream));
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
@@ -170,6 +169,17 @@ rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const r
   });
   const int nworkers = std::min(n, 16);
   std::atomic<int> next{0};
+  // admission by estimated footprint against the device memory free at the
+  // start (a request too large for the budget runs when it is alone)
+  size_t free_b = 0, total_b = 0;
+  RID_HIP(hipMemGetInfo(&free_b, &total_b));
+  const uint64_t budget = (uint64_t)(0.8 * (double)free_b);
+  std::mutex amu;
+  std::condition_variable acv;
+  uint64_t used = 0;
+  int running = 0;
+  const Clock::time_point t0 = Clock::now();
+  auto ms = [&] { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); };
   {
     DeferFree defer(ctx);
     Batcher batcher(ctx);
@@ -181,7 +191,25 @@ rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const r
           const ExecCfg ex{ws.s, &batcher};
           for (int q = next++; q < n; q = next++) {
             const int i = order[q];
+            const uint64_t need = request_footprint(probs[i], reqs[i]);
+            {
+              std::unique_lock<std::mutex> lk(amu);
+              acv.wait(lk, [&] { return running == 0 || used + need <= budget; });
+              used += need;
+              running += 1;
+            }
+            results[i].t_arrival_ms = 0.0;
+            results[i].t_admit_ms = ms();
             run_one(probs[i], reqs[i], &results[i], ex);
+            results[i].t_done_ms = ms();
+            // hand back what this solve freed before admitting more work
+            reap_graveyard(ctx, false);
+            {
+              std::lock_guard<std::mutex> lk(amu);
+              used -= need;
+              running -= 1;
+            }
+            acv.notify_all();
           }
         } catch (const Error& e) {
           std::lock_guard<std::mutex> g(g_err_mu);
@@ -252,22 +280,12 @@ void worker_body(rid_server* s, const ExecCfg& ex) {
     s->cv_work.notify_all();  // the next request may fit too
     lk.unlock();
     const rid_status st = run_one(q->P, q->r, q->res, ex);
-    uint64_t parked;
-    {
-      std::lock_guard<std::mutex> g(s->ctx->grave_mu);
-      parked = s->ctx->grave_bytes;
-    }
+    reap_graveyard(s->ctx, false);
     lk.lock();
     s->used_bytes -= q->bytes;
     s->running -= 1;
-    const bool idle = s->running == 0;
     finish(s, q, st);
     s->cv_work.notify_all();
-    if (idle || parked > kFlushBytes) {
-      lk.unlock();
-      flush_graveyard(s->ctx);
-      lk.lock();
-    }
   }
 }
 
@@ -290,6 +308,13 @@ rid_status server_submit(rid_server* s, rid_problem* P, const rid_request* r, ri
   if (!P || !r || !res || !ticket) return RID_ERR_INVALID_ARG;
   if (P->ctx != s->ctx) return RID_ERR_INVALID_ARG;
   if (r->kind != 0 && r->kind != 1) return RID_ERR_INVALID_ARG;
+  try {
+    prepare_problem(P, r->opts);
+  } catch (const Error& e) {
+    std::lock_guard<std::mutex> g(g_err_mu);
+    s->ctx->last_error = e.what();
+    return e.code;
+  }
   Req* q = new Req();
   q->P = P;
   q->r = *r;

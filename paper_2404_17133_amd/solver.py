@@ -64,13 +64,15 @@ class Context:
             def _alloc(user, nbytes):
                 try:
                     t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
-                except Exception:  # out of memory: the library reports RID_ERR_NO_MEMORY
+                except Exception as e:  # out of memory: the library reports RID_ERR_NO_MEMORY
+                    blocks["last_failure"] = "%d bytes: %s" % (int(nbytes), str(e).splitlines()[0][:300])
                     return None
                 blocks[t.data_ptr()] = t
                 return t.data_ptr()
 
             def _free(user, p):
-                blocks.pop(int(p) if p else 0, None)
+                if p:
+                    blocks.pop(int(p), None)
 
             self._alloc_ref = (B.ALLOC_FN(_alloc), B.FREE_FN(_free))
             alloc = B.rid_allocator(None, self._alloc_ref[0], self._alloc_ref[1])
@@ -96,6 +98,13 @@ class Context:
             s = arr[i]
             out[s.name.decode()] = dict(launches=int(s.launches), ms=s.total_ms, flops=s.flops, bytes=s.bytes)
         return out
+
+    def last_error(self) -> str:
+        """The library's last error text, and the allocator's last failure."""
+        msg = B.lib.rid_last_error(self.handle).decode() if getattr(self, "handle", None) else ""
+        if "last_failure" in self._blocks:
+            msg += " (allocator: %s)" % self._blocks["last_failure"]
+        return msg
 
     def check(self, s: int, ok=(B.RID_OK,)):
         if s not in ok:
@@ -308,12 +317,18 @@ def batch_solve(ctx: Context, problems: Sequence[Problem], requests: Sequence[B.
         if "alpha" in k:
             rs[i].alpha_host = _dptr(k["alpha"])
         rs[i].resid_host = _dptr(k["resid"])
+    # the library admits solves by the device memory it sees free: hand back
+    # blocks that PyTorch caches but does not use
+    torch.cuda.synchronize(ctx.device)
+    torch.cuda.empty_cache()
     s = B.lib.rid_batch_solve(ctx.handle, n, ctypes.cast(hp, ctypes.POINTER(ctypes.c_void_p)), rq, rs)
     out = []
     for i in range(n):
         d = dict(keeps[i])
         d["status"] = rs[i].status
         d["stats"] = rs[i].stats.as_dict()
+        d["t_start_ms"] = rs[i].t_admit_ms
+        d["t_done_ms"] = rs[i].t_done_ms
         out.append(d)
     return s, out
 

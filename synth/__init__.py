@@ -18,4 +18,6 @@ from .generate import (  # noqa: F401
     make_block,
     config_sizes,
     molecule_sizes,
+    batch_member,
+    serve_trace,
 )

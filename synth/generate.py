@@ -306,3 +306,44 @@ def molecule_sizes(no: int):
     """
     return dict(no=no, nv=4 * no, naux=20 * no, naux_ris=int(round(4.5 * no)),
                 naux_ris_k=max(1, int(round(0.5 * no))))
+
+
+def batch_member(m: int) -> dict:
+    """Molecule m of the batched workload (64 molecules of uneven size).
+
+    no = round(exp(U[ln 20, ln 200])) with the sizes of molecule_sizes, and
+    k drawn uniformly from {5, 10, 20}; seed 300 + m.
+    """
+    u = counter_uniforms(300 + m, 7, 0, 2)
+    no = int(round(math.exp(math.log(20.0) + float(u[0]) * (math.log(200.0) - math.log(20.0)))))
+    k = (5, 10, 20)[min(2, int(float(u[1]) * 3.0))]
+    d = molecule_sizes(no)
+    d.update(k=k, seed=300 + m)
+    return d
+
+
+def serve_trace(n: int, seed: int = 400, no_min: int = 20, no_max: int = 300) -> list:
+    """A served request stream: n requests in arrival order.
+
+    Request r (seed 400000 + r): no log-uniform in [no_min, no_max] with the
+    sizes of molecule_sizes; 70% eigen-solves (TDA or RPA with probability
+    1/2 each, k uniform in 5..20), 30% polarizabilities (3 right-hand sides,
+    3 frequencies uniform in [0, 0.3] Ha, sorted).  `gap` is an Exp(1)
+    inter-arrival draw, to be divided by the arrival rate.
+    """
+    out = []
+    for r in range(n):
+        u = counter_uniforms(seed * 1000 + r, 9, 0, 8)
+        no = int(round(math.exp(math.log(no_min) + float(u[0]) * (math.log(no_max) - math.log(no_min)))))
+        d = molecule_sizes(no)
+        d["seed"] = seed * 1000 + r
+        d["gap"] = -math.log(float(u[1]))
+        if float(u[2]) < 0.7:
+            d["kind"] = "eigen"
+            d["mode"] = "tda" if float(u[3]) < 0.5 else "rpa"
+            d["k"] = 5 + min(15, int(float(u[4]) * 16.0))
+        else:
+            d["kind"] = "polarizability"
+            d["omegas"] = sorted(0.3 * float(x) for x in u[5:8])
+        out.append(d)
+    return out

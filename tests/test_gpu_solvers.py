@@ -102,3 +102,20 @@ def test_not_converged_and_near_singular():
         prob.polarizability(pm, [5.0], "diag")
     assert e.value.status == -8
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_rpa_restart_config0(precision):
+    """A small subspace limit forces restarts (collapse onto the Ritz pairs'
+    Z and Z'); the roots still match the oracle."""
+    p, op = config0()
+    ref = eigen_rpa(op, 5, "diag", tol=1e-8)
+    ctx, prob = gpu_problem(p)
+    print("rpa restart", precision, flush=True)
+    out = prob.eigen(5, "rpa", "diag", precision, m_max=44)
+    assert out["status"] == 0
+    assert np.abs(out["omega"] - ref.omega).max() < 1e-6
+    assert out["stats"]["n_mv"] > 44  # more products than the subspace holds: it restarted
+    x, y = out["x"].cpu().numpy(), out["y"].cpu().numpy()
+    np.testing.assert_allclose(np.sum(x * x, axis=1) - np.sum(y * y, axis=1), 1.0, atol=1e-8)
+    ctx.close()

@@ -221,3 +221,24 @@ def test_config0_both_preconditioners_reach_dense_roots():
         assert res.converged
         # converged to 1e-5 in the residual: Kato-Temple gives ~1e-9 here
         np.testing.assert_allclose(res.omega, ref, atol=1e-8)
+
+
+@pytest.mark.parametrize("mode", ["tda", "rpa"])
+def test_restart_reaches_dense_roots(mode):
+    """A subspace limit far below the iteration count forces restarts onto the
+    leading Ritz vectors (k + n_extra of them; for full TDDFT their Z and Z');
+    the roots still converge to the dense ones."""
+    _, op = small(no=8, nv=32, naux=160, naux_ris=36, seed=5)
+    a, apb, amb = dense(op)
+    if mode == "tda":
+        ref = np.linalg.eigh(a)[0][:5]
+        res = eigen_tda(op, 5, "diag", tol=1e-8, m_max=30)
+        full = eigen_tda(op, 5, "diag", tol=1e-8)
+    else:
+        ref = rpa_dense_roots(apb, amb)[0][:5]
+        res = eigen_rpa(op, 5, "diag", tol=1e-8, m_max=40)
+        full = eigen_rpa(op, 5, "diag", tol=1e-8)
+    assert res.converged
+    assert res.n_mv > 40  # more products than the subspace holds: it restarted
+    np.testing.assert_allclose(res.omega, ref, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(full.omega, ref, rtol=0, atol=1e-10)

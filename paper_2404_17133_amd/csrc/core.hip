@@ -676,6 +676,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.sC1 = J.s_per_p;
         g.alpha = 1.0;
         g.mode = GEMM_STORE;
+        g.order = ORDER_ZIN;  // each XCD keeps its share of Xt in L2 across the batch of P
         ps.flops += 2.0 * J.no_a * (double)J.nvec * J.nv_a * J.no_a * pcc;
         ps.bytes += esz * ((double)pcc * J.no_a * J.no_a + (double)J.nvec * J.nv_a * J.no_a + (double)pcc * J.s_per_p);
         plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.nv_a, pcc, 1, J.no_a, false, st);
@@ -708,6 +709,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.sCs = J.part_elems;
         g.alpha = 1.0;
         g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
+        g.order = ORDER_NM;  // a row block of S^P meets every column block of B^P_ab in L2
         ps.flops += 2.0 * J.rows * (double)J.nv_a * J.nv_a * pcc;
         ps.bytes += esz * ((double)pcc * J.s_per_p + (double)pcc * J.nv_a * J.nv_a) +
                     asz * J.part_elems * (first ? 1.0 : 2.0);
@@ -743,6 +745,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.sC1 = J.q_per_p;
         g.alpha = 1.0;
         g.mode = GEMM_STORE;
+        g.order = ORDER_ZIN;
         ps.flops += 2.0 * J.no_a * (double)J.nvec * J.no_a * J.nv_a * pcc;
         ps.bytes += esz * ((double)pcc * J.no_a * J.nv_a + (double)J.nvec * J.no_a * J.nv_a + (double)pcc * J.q_per_p);
         plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, pcc, 1, J.nv_a, false, st);
@@ -775,6 +778,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.sCs = J.part_elems;
         g.alpha = 1.0;
         g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
+        g.order = ORDER_NM;
         ps.flops += 2.0 * J.rows * (double)J.nv_a * J.no_a * pcc;
         ps.bytes += esz * ((double)pcc * J.q_per_p + (double)pcc * J.nv_a * J.no_a) +
                     asz * J.part_elems * (first ? 1.0 : 2.0);

@@ -4,8 +4,8 @@
 // WM x WN sub-tile made of MFMA atoms (32x32 for f32/bf16, 16x16 for f64).
 // Every K stage moves 128 bytes of K per operand row (32 f32, 16 f64, 64
 // bf16) from global memory to LDS, double-buffered with one barrier per
-// stage.  (Measured on gfx950: a second stage of register prefetch and an
-// XCD-aware re-mapping of workgroups to tiles did not help at these shapes.)  LDS rows are padded
+// stage.  (Measured on gfx950: a second stage of register prefetch did not
+// help at these shapes.)  LDS rows are padded
 // by 16 bytes (stride 144 B) so that the 16-byte fragment reads of 16
 // consecutive rows hit distinct banks.  The K order inside a stage is
 // permuted so that each lane reads one contiguous slice per operand row: lane
@@ -255,34 +255,81 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
   }
 }
 
+constexpr int kXcds = 8;
+
+// Position in the tile walk of workgroup w of a launch of `total`: the
+// workgroups that land on one XCD (w = x mod 8, dealt in turn) take one
+// contiguous range of the walk, in dispatch order.
+__device__ inline long xcd_walk(long w, long total) {
+  const long q = total / kXcds, r = total % kXcds;
+  const long x = w % kXcds;
+  return x * q + (x < r ? x : r) + w / kXcds;
+}
+
+// Tile coordinates of walk position t (see GemmOrder).
+__device__ inline void walk_decode(int order, long t, int tiles_m, int tiles_n, int nz, int& tm, int& tn, int& z,
+                                   int& split) {
+  const long tiles = (long)tiles_m * tiles_n;
+  if (order == ORDER_ZIN) {
+    tm = (int)(t % tiles_m);
+    long r = t / tiles_m;
+    z = (int)(r % nz);
+    r /= nz;
+    tn = (int)(r % tiles_n);
+    split = (int)(r / tiles_n);
+    return;
+  }
+  const long tile = t % tiles;
+  const long r = t / tiles;
+  z = (int)(r % nz);
+  split = (int)(r / nz);
+  if (order == ORDER_NM) {
+    tn = (int)(tile % tiles_n);
+    tm = (int)(tile / tiles_n);
+  } else {
+    tm = (int)(tile % tiles_m);
+    tn = (int)(tile / tiles_m);
+  }
+}
+
 template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
-__global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmParams p) {
+__global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmParams p, int nz, long total) {
   const int tiles_m = (p.M + BM - 1) / BM;
-  gemm_tile<T, BM, BN, WM, WN, VEC>(p, blockIdx.x % tiles_m, blockIdx.x / tiles_m, blockIdx.y, blockIdx.z);
+  const int tiles_n = (p.N + BN - 1) / BN;
+  int tm, tn, z, split;
+  walk_decode(p.order, xcd_walk(blockIdx.x, total), tiles_m, tiles_n, nz, tm, tn, z, split);
+  gemm_tile<T, BM, BN, WM, WN, VEC>(p, tm, tn, z, split);
 }
 
 // Device descriptor of one member of a grouped launch.
 struct GroupDesc {
   GemmParams p;
-  int tiles_m, tiles_mn, nz, pad;
+  int tiles_m, tiles_n, nz, pad;
   long begin;  // index of the member's first tile in the launch
 };
 
-// Persistent grouped GEMM: the workgroups walk the concatenated tile lists of
-// all members (tile fastest, then batch, then split, the order in which the
-// single-GEMM grid is dispatched), each taking every gridDim.x-th tile.
+// Persistent grouped GEMM: the workgroups walk the concatenated tile walks
+// of all members, each taking every gridDim.x-th position.  With a grid that
+// is a multiple of the XCD count, a workgroup stays on one XCD, and the
+// positions are re-mapped as in the single-GEMM kernel so that each XCD
+// covers one contiguous range of the concatenated walk.
 template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
 __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_grouped_kernel(const GroupDesc* __restrict__ gd,
                                                                                int ngroups, long total) {
-  int g = 0;
   for (long b = blockIdx.x; b < total; b += gridDim.x) {
-    while (g + 1 < ngroups && b >= gd[g + 1].begin) ++g;
-    const GemmParams p = gd[g].p;
-    const long local = b - gd[g].begin;
-    const int tiles_m = gd[g].tiles_m, tiles_mn = gd[g].tiles_mn, nz = gd[g].nz;
-    const int tile = (int)(local % tiles_mn);
-    const long rest = local / tiles_mn;
-    gemm_tile<T, BM, BN, WM, WN, VEC>(p, tile % tiles_m, tile / tiles_m, (int)(rest % nz), (int)(rest / nz));
+    const long t = xcd_walk(b, total);
+    int lo = 0, hi = ngroups - 1;  // member holding position t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (gd[mid].begin <= t)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const GemmParams p = gd[lo].p;
+    int tm, tn, z, split;
+    walk_decode(p.order, t - gd[lo].begin, gd[lo].tiles_m, gd[lo].tiles_n, gd[lo].nz, tm, tn, z, split);
+    gemm_tile<T, BM, BN, WM, WN, VEC>(p, tm, tn, z, split);
   }
 }
 
@@ -306,24 +353,26 @@ struct Cfgs<bf16_t> {
 };
 
 template <typename T, int BM, int BN, int WM, int WN, int FAM>
-void launch_fam(const GemmParams& p, dim3 grid, bool vec, hipStream_t stream) {
+void launch_fam(const GemmParams& p, int nz, long total, bool vec, hipStream_t stream) {
   if (vec)
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, true, FAM>), grid, dim3(256), 0, stream, p);
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, true, FAM>), dim3((unsigned)total), dim3(256), 0, stream, p,
+                       nz, total);
   else
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, false, FAM>), grid, dim3(256), 0, stream, p);
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, false, FAM>), dim3((unsigned)total), dim3(256), 0, stream,
+                       p, nz, total);
 }
 
 template <typename T, int BM, int BN, int WM, int WN>
 void launch_cfg(const GemmParams& p, int nz, int nsplit, bool vec, hipStream_t stream, int family) {
-  const int tiles = ceil_div(p.M, BM) * ceil_div(p.N, BN);
-  dim3 grid(tiles, nz, nsplit);
+  const long total = (long)ceil_div(p.M, BM) * ceil_div(p.N, BN) * nz * nsplit;
+  RID_CHECK(total < (1L << 31), RID_ERR_SHAPE, "gemm: grid too large");
   switch (family) {
-    case GF_COUL: launch_fam<T, BM, BN, WM, WN, GF_COUL>(p, grid, vec, stream); break;
-    case GF_EXCH_S: launch_fam<T, BM, BN, WM, WN, GF_EXCH_S>(p, grid, vec, stream); break;
-    case GF_EXCH_W: launch_fam<T, BM, BN, WM, WN, GF_EXCH_W>(p, grid, vec, stream); break;
-    case GF_EXCH_Q: launch_fam<T, BM, BN, WM, WN, GF_EXCH_Q>(p, grid, vec, stream); break;
-    case GF_EXCH_WP: launch_fam<T, BM, BN, WM, WN, GF_EXCH_WP>(p, grid, vec, stream); break;
-    default: launch_fam<T, BM, BN, WM, WN, GF_GENERIC>(p, grid, vec, stream); break;
+    case GF_COUL: launch_fam<T, BM, BN, WM, WN, GF_COUL>(p, nz, total, vec, stream); break;
+    case GF_EXCH_S: launch_fam<T, BM, BN, WM, WN, GF_EXCH_S>(p, nz, total, vec, stream); break;
+    case GF_EXCH_W: launch_fam<T, BM, BN, WM, WN, GF_EXCH_W>(p, nz, total, vec, stream); break;
+    case GF_EXCH_Q: launch_fam<T, BM, BN, WM, WN, GF_EXCH_Q>(p, nz, total, vec, stream); break;
+    case GF_EXCH_WP: launch_fam<T, BM, BN, WM, WN, GF_EXCH_WP>(p, nz, total, vec, stream); break;
+    default: launch_fam<T, BM, BN, WM, WN, GF_GENERIC>(p, nz, total, vec, stream); break;
   }
 }
 
@@ -366,6 +415,7 @@ bool vec_ok(const GemmParams& p) {
 
 void check_params(const GemmParams& p, int nz, int nsplit) {
   RID_CHECK(p.np >= 1 && p.pps >= 1 && p.nz2 >= 1, RID_ERR_INTERNAL, "gemm: bad batch counts");
+  RID_CHECK(p.order >= ORDER_MN && p.order <= ORDER_ZIN, RID_ERR_INTERNAL, "gemm: bad tile order");
   RID_CHECK((long)nsplit * p.pps >= p.np, RID_ERR_INTERNAL, "gemm: splits do not cover batches");
   RID_CHECK(ceil_div_l(p.M, 64) * ceil_div_l(p.N, 64) < (1L << 31), RID_ERR_SHAPE, "gemm: grid too large");
   RID_CHECK(nz < 65536 && nsplit < 65536, RID_ERR_SHAPE, "gemm: batch grid too large");
@@ -393,11 +443,11 @@ void gemm_grouped(const GemmGroup* mem, int n, int cfg, int family, void* desc_d
       GroupDesc& d = hd[cnt[0] + cnt[1]];
       d.p = p;
       d.tiles_m = ceil_div(p.M, bm);
-      d.tiles_mn = d.tiles_m * ceil_div(p.N, bn);
+      d.tiles_n = ceil_div(p.N, bn);
       d.nz = mem[i].nz;
       d.pad = 0;
       d.begin = total[pass];
-      total[pass] += (long)d.tiles_mn * mem[i].nz * mem[i].nsplit;
+      total[pass] += (long)d.tiles_m * d.tiles_n * mem[i].nz * mem[i].nsplit;
       ++cnt[pass];
     }
   }
@@ -408,7 +458,9 @@ void gemm_grouped(const GemmGroup* mem, int n, int cfg, int family, void* desc_d
   for (int pass = 0; pass < 2; ++pass) {
     if (cnt[pass] == 0) continue;
     const GroupDesc* base = dd + (pass == 0 ? 0 : cnt[0]);
-    const int grid = (int)std::min<long>(total[pass], std::max(grid_cap, 1));
+    // a multiple of the XCD count keeps every workgroup on one XCD
+    const int cap = std::max(kXcds, grid_cap / kXcds * kXcds);
+    const int grid = (int)std::min<long>(total[pass], cap);
     switch (cfg) {
       case 0: launch_grouped_cfg<T, 128, 128, 64, 64>(base, cnt[pass], total[pass], grid, pass == 0, family, stream); break;
       case 1: launch_grouped_cfg<T, 64, 64, 32, 32>(base, cnt[pass], total[pass], grid, pass == 0, family, stream); break;

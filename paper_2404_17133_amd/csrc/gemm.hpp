@@ -33,8 +33,19 @@ struct GemmParams {
   long sA1, sA2, sB1, sB2, sC1, sC2;
   long sCs;  // stride between split outputs (partial modes)
   double alpha;
-  int mode;  // GemmMode
+  int mode;   // GemmMode
+  int order;  // GemmOrder: the order in which workgroups walk the tiles
 };
+
+// Tile walk of a launch.  Workgroups are dealt to the chip's 8 XCDs in turn;
+// every launch re-maps them so that each XCD takes one contiguous range of
+// the walk below, whose fastest index keeps the operand that most tiles
+// share in that XCD's L2.
+//   ORDER_MN: tm fastest, then tn, batch, split (B row block reused);
+//   ORDER_NM: tn fastest, then tm, batch, split (A row block reused);
+//   ORDER_ZIN: tm fastest, then batch, then tn, split (B row block reused
+//              across all batches).
+enum GemmOrder { ORDER_MN = 0, ORDER_NM = 1, ORDER_ZIN = 2 };
 
 // Element-type tag for bf16 operands stored as raw uint16_t.
 struct bf16_t {};

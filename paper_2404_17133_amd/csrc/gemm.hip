@@ -138,26 +138,67 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
   const long lda = p.lda, ldb = p.ldb, sAp = p.sAp, sBp = p.sBp;
   const int M = p.M, N = p.N, K = p.K;
 
-  auto gload = [&](int t, uint4 (&pre)[CPT]) {
-    const int pp = pbeg + t / nkt;
-    const int k = (t % nkt) * BK + kc * VW;
+  // Chunk i of a thread holds row rbase + 32 i of the stacked (A; B) tile:
+  // A rows for i < NA, B rows after.
+  constexpr int NA = BM / 32;
+  // 16-byte loads go through buffer resources based at the tile's first row
+  // of the current batch: the per-thread byte offsets are fixed for the
+  // tile, the K position of the stage is a uniform offset, and rows past M
+  // (N) or chunks past K take an offset beyond the resource's range, which
+  // the hardware returns as zeros - no branches, no 64-bit address math per
+  // stage.
+  constexpr int kOob = (int)0x80000000;
+  int voff[CPT];
+  if constexpr (VEC) {
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
-      const int r = rbase + 32 * i;
-      const E_t* src;
-      bool ok;
-      if (r < BM) {
-        const int m = m0 + r;
-        ok = m < M;
-        src = Ab + pp * sAp + (long)m * lda + k;
-      } else {
-        const int n = n0 + (r - BM);
-        ok = n < N;
-        src = Bb + pp * sBp + (long)n * ldb + k;
+      const bool a_row = i < NA;
+      const int r = rbase + 32 * (a_row ? i : i - NA);
+      const bool ok = a_row ? (m0 + r < M) : (n0 + r < N);
+      const long ld = a_row ? lda : ldb;
+      voff[i] = ok ? (int)(((long)r * ld + kc * VW) * (long)sizeof(E_t)) : kOob;
+    }
+  }
+  int pcur = pbeg, kcur = 0;  // batch and K position of the next stage to load
+
+  auto gload = [&](int t, uint4 (&pre)[CPT]) {
+    if constexpr (VEC) {
+      (void)t;
+      const E_t* abase = Ab + (long)pcur * sAp + (long)m0 * lda;
+      const E_t* bbase = Bb + (long)pcur * sBp + (long)n0 * ldb;
+      const __amdgpu_buffer_rsrc_t ra =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<E_t*>(abase), (short)0, 0x7fffffff, 0x00020000);
+      const __amdgpu_buffer_rsrc_t rb =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<E_t*>(bbase), (short)0, 0x7fffffff, 0x00020000);
+      const bool kin = kcur + kc * VW < K;
+      const int soff = kcur * (int)sizeof(E_t);
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(i < NA ? ra : rb, kin ? voff[i] : kOob, soff, 0);
+        pre[i] = make_uint4(v[0], v[1], v[2], v[3]);
       }
-      if constexpr (VEC) {
-        pre[i] = (ok && k < K) ? *reinterpret_cast<const uint4*>(src) : make_uint4(0, 0, 0, 0);
-      } else {
+      kcur += BK;
+      if (kcur >= nkt * BK) {
+        kcur = 0;
+        ++pcur;
+      }
+    } else {
+      const int pp = pbeg + t / nkt;
+      const int k = (t % nkt) * BK + kc * VW;
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        const int r = rbase + 32 * i;
+        const E_t* src;
+        bool ok;
+        if (i < NA) {
+          const int m = m0 + r;
+          ok = m < M;
+          src = Ab + pp * sAp + (long)m * lda + k;
+        } else {
+          const int n = n0 + (r - BM);
+          ok = n < N;
+          src = Bb + pp * sBp + (long)n * ldb + k;
+        }
         union { uint4 v; E_t e[VW]; } u;
 #pragma unroll
         for (int e = 0; e < VW; ++e) u.e[e] = (ok && k + e < K) ? src[e] : E_t(0);
@@ -266,39 +307,39 @@ __device__ inline long xcd_walk(long w, long total) {
   return x * q + (x < r ? x : r) + w / kXcds;
 }
 
+struct TileCoord {
+  int tm, tn, z, split;
+};
+
 // Tile coordinates of walk position t (see GemmOrder).
-__device__ inline void walk_decode(int order, long t, int tiles_m, int tiles_n, int nz, int& tm, int& tn, int& z,
-                                   int& split) {
-  const long tiles = (long)tiles_m * tiles_n;
+__device__ inline TileCoord walk_decode(int order, long t, int tiles_m, int tiles_n, int nz) {
+  TileCoord c;
   if (order == ORDER_ZIN) {
-    tm = (int)(t % tiles_m);
+    c.tm = (int)(t % tiles_m);
     long r = t / tiles_m;
-    z = (int)(r % nz);
+    c.z = (int)(r % nz);
     r /= nz;
-    tn = (int)(r % tiles_n);
-    split = (int)(r / tiles_n);
-    return;
+    c.tn = (int)(r % tiles_n);
+    c.split = (int)(r / tiles_n);
+    return c;
   }
+  const long tiles = (long)tiles_m * tiles_n;
   const long tile = t % tiles;
   const long r = t / tiles;
-  z = (int)(r % nz);
-  split = (int)(r / nz);
-  if (order == ORDER_NM) {
-    tn = (int)(tile % tiles_n);
-    tm = (int)(tile / tiles_n);
-  } else {
-    tm = (int)(tile % tiles_m);
-    tn = (int)(tile / tiles_m);
-  }
+  c.z = (int)(r % nz);
+  c.split = (int)(r / nz);
+  const bool nm = order == ORDER_NM;
+  c.tn = (int)(nm ? tile % tiles_n : tile / tiles_m);
+  c.tm = (int)(nm ? tile / tiles_n : tile % tiles_m);
+  return c;
 }
 
 template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
 __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmParams p, int nz, long total) {
   const int tiles_m = (p.M + BM - 1) / BM;
   const int tiles_n = (p.N + BN - 1) / BN;
-  int tm, tn, z, split;
-  walk_decode(p.order, xcd_walk(blockIdx.x, total), tiles_m, tiles_n, nz, tm, tn, z, split);
-  gemm_tile<T, BM, BN, WM, WN, VEC>(p, tm, tn, z, split);
+  const TileCoord c = walk_decode(p.order, xcd_walk(blockIdx.x, total), tiles_m, tiles_n, nz);
+  gemm_tile<T, BM, BN, WM, WN, VEC>(p, c.tm, c.tn, c.z, c.split);
 }
 
 // Device descriptor of one member of a grouped launch.
@@ -327,9 +368,8 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_grouped_kernel(
         hi = mid - 1;
     }
     const GemmParams p = gd[lo].p;
-    int tm, tn, z, split;
-    walk_decode(p.order, t - gd[lo].begin, gd[lo].tiles_m, gd[lo].tiles_n, gd[lo].nz, tm, tn, z, split);
-    gemm_tile<T, BM, BN, WM, WN, VEC>(p, tm, tn, z, split);
+    const TileCoord c = walk_decode(p.order, t - gd[lo].begin, gd[lo].tiles_m, gd[lo].tiles_n, gd[lo].nz);
+    gemm_tile<T, BM, BN, WM, WN, VEC>(p, c.tm, c.tn, c.z, c.split);
   }
 }
 

@@ -535,6 +535,153 @@ __global__ __launch_bounds__(DB) void lu_solve_kernel(double* mats, double* rhs,
   }
 }
 
+// Gaussian elimination with partial pivoting on column-major systems
+// (a(i, k) at a[k m + i]), one system per workgroup of LB threads.  Thread t
+// owns rows t, t + LB, ...: it computes their multipliers and updates them,
+// reading the pivot row by broadcast and its own rows with coalesced
+// accesses, so that a column needs two barriers (pivot choice, row swap).
+// The pivot search of column j + 1 visits exactly the rows each thread
+// updated at column j, so no barrier separates the two.
+constexpr int LB = 256;
+
+__device__ inline double guard_pivot(double p) { return fabs(p) < 1e-300 ? (p < 0.0 ? -1e-300 : 1e-300) : p; }
+
+__global__ __launch_bounds__(LB) void lu_cm_kernel(double* mats, double* rhs, int m) {
+  __shared__ double rv[LB / 64];
+  __shared__ int ri[LB / 64];
+  double* a = mats + (long)blockIdx.x * m * m;
+  double* g = rhs + (long)blockIdx.x * m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j < m; ++j) {
+    // pivot: argmax |a(i, j)| over i >= j (ties to the smaller index)
+    double best = -1.0;
+    int bi = m;
+    for (int i = j + tid; i < m; i += LB) {
+      const double v = fabs(a[(long)j * m + i]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      rv[wave] = best;
+      ri[wave] = bi;
+    }
+    __syncthreads();
+    double pb = -1.0;
+    int p = j;
+    for (int w = 0; w < LB / 64; ++w)
+      if (rv[w] > pb || (rv[w] == pb && ri[w] < p)) {
+        pb = rv[w];
+        p = ri[w];
+      }
+    if (p >= m) p = j;
+    if (p != j) {
+      for (int k = tid; k < m; k += LB) {
+        const double t = a[(long)k * m + j];
+        a[(long)k * m + j] = a[(long)k * m + p];
+        a[(long)k * m + p] = t;
+      }
+      if (tid == 0) {
+        const double t = g[j];
+        g[j] = g[p];
+        g[p] = t;
+      }
+    }
+    __syncthreads();
+    const double pv = guard_pivot(a[(long)j * m + j]);
+    const double gj = g[j];
+    for (int i = j + 1 + tid; i < m; i += LB) {
+      const double l = a[(long)j * m + i] / pv;
+      a[(long)j * m + i] = l;
+      for (int k = j + 1; k < m; ++k) a[(long)k * m + i] -= l * a[(long)k * m + j];
+      g[i] -= l * gj;
+    }
+  }
+  // back substitution with U (diagonal guarded as in the elimination)
+  for (int j = m - 1; j >= 0; --j) {
+    __syncthreads();
+    const double yj = g[j] / guard_pivot(a[(long)j * m + j]);
+    __syncthreads();
+    if (tid == 0) g[j] = yj;
+    for (int i = tid; i < j; i += LB) g[i] -= a[(long)j * m + i] * yj;
+  }
+}
+
+// Pair systems of the inner full-TDDFT solve.  System q of right-hand side
+// b = sys_b[q]: type 0 (shift s != 0): (t- t+ - s^2 I) y = t- g1 + s g2;
+// type 1 (s = 0): t+ y = g1; type 2 (s = 0): t- y' = g2.  Matrices are
+// written column-major for lu_cm_kernel.
+__global__ void pair_mats_kernel(const double* __restrict__ P, const double* __restrict__ tp,
+                                 const double* __restrict__ tm, int ld, int m, const int* __restrict__ sys_type,
+                                 const double* __restrict__ sys_shift, double* __restrict__ mats) {
+  const int q = blockIdx.y;
+  const int type = sys_type[q];
+  const double s2 = sys_shift[q] * sys_shift[q];
+  double* out = mats + (long)q * m * m;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m * m; e += gridDim.x * blockDim.x) {
+    const int k = e / m, i = e - k * m;  // out(i, k) at k m + i
+    double v;
+    if (type == 0)
+      v = P[(long)i * m + k] - (i == k ? s2 : 0.0);
+    else if (type == 1)
+      v = tp[(long)i * ld + k];
+    else
+      v = tm[(long)i * ld + k];
+    out[e] = v;
+  }
+}
+
+__global__ void pair_rhs_kernel(const double* __restrict__ g, int ldg, const double* __restrict__ tg,
+                                const int* __restrict__ sys_b, const int* __restrict__ sys_type,
+                                const double* __restrict__ sys_shift, int nsys, int m, double* __restrict__ rhs) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsys * m) return;
+  const int q = t / m, i = t - q * m;
+  const int b = sys_b[q], type = sys_type[q];
+  const double* g1 = g + (long)b * ldg;
+  const double* g2 = g1 + m;
+  double v;
+  if (type == 0)
+    v = tg[(long)b * m + i] + sys_shift[q] * g2[i];
+  else if (type == 1)
+    v = g1[i];
+  else
+    v = g2[i];
+  rhs[(long)q * m + i] = v;
+}
+
+// Write the solutions back: type 0 gives y and y' = (t+ y - g1) / s (yt =
+// y t+), type 1 gives y, type 2 gives y'.
+__global__ void pair_unpack_kernel(double* __restrict__ g, int ldg, const double* __restrict__ sol,
+                                   const double* __restrict__ yt, const int* __restrict__ sys_b,
+                                   const int* __restrict__ sys_type, const double* __restrict__ sys_shift, int nsys,
+                                   int m) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsys * m) return;
+  const int q = t / m, i = t - q * m;
+  const int b = sys_b[q], type = sys_type[q];
+  double* g1 = g + (long)b * ldg;
+  double* g2 = g1 + m;
+  const double y = sol[(long)q * m + i];
+  if (type == 0) {
+    g2[i] = (yt[(long)q * m + i] - g1[i]) / sys_shift[q];
+    g1[i] = y;
+  } else if (type == 1) {
+    g1[i] = y;
+  } else {
+    g2[i] = y;
+  }
+}
+
 // Tiled small GEMM, 16x16 tiles.
 __global__ void small_gemm_kernel(int ta, int tb, int m, int n, int k, double alpha, const double* __restrict__ A,
                                   int lda, const double* __restrict__ B, int ldb, double beta, double* C, int ldc) {
@@ -666,6 +813,32 @@ void small_chol(double* a, int m, int lda, int* info, hipStream_t s) {
 void small_lu_solve(double* mats, double* rhs, int m, int nb, hipStream_t s) {
   if (m <= 0 || nb <= 0) return;
   hipLaunchKernelGGL(lu_solve_kernel, dim3(nb), dim3(DB), 0, s, mats, rhs, m);
+  RID_HIP(hipGetLastError());
+}
+
+void small_lu_solve_cm(double* mats, double* rhs, int m, int nb, hipStream_t s) {
+  if (m <= 0 || nb <= 0) return;
+  hipLaunchKernelGGL(lu_cm_kernel, dim3(nb), dim3(LB), 0, s, mats, rhs, m);
+  RID_HIP(hipGetLastError());
+}
+
+void pair_systems_build(const double* P, const double* tp, const double* tm, int ld, int m, const int* sys_b,
+                        const int* sys_type, const double* sys_shift, int nsys, const double* g, int ldg,
+                        const double* tg, double* mats, double* rhs, hipStream_t s) {
+  if (m <= 0 || nsys <= 0) return;
+  RID_CHECK(nsys < 65536, RID_ERR_SHAPE, "too many pair systems");
+  dim3 grid((unsigned)std::min(ceil_div(m * m, 256), 256), (unsigned)nsys);
+  hipLaunchKernelGGL(pair_mats_kernel, grid, dim3(256), 0, s, P, tp, tm, ld, m, sys_type, sys_shift, mats);
+  hipLaunchKernelGGL(pair_rhs_kernel, dim3(ceil_div(nsys * m, 256)), dim3(256), 0, s, g, ldg, tg, sys_b, sys_type,
+                     sys_shift, nsys, m, rhs);
+  RID_HIP(hipGetLastError());
+}
+
+void pair_systems_unpack(double* g, int ldg, const double* sol, const double* yt, const int* sys_b,
+                         const int* sys_type, const double* sys_shift, int nsys, int m, hipStream_t s) {
+  if (m <= 0 || nsys <= 0) return;
+  hipLaunchKernelGGL(pair_unpack_kernel, dim3(ceil_div(nsys * m, 256)), dim3(256), 0, s, g, ldg, sol, yt, sys_b,
+                     sys_type, sys_shift, nsys, m);
   RID_HIP(hipGetLastError());
 }
 

@@ -398,7 +398,7 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
     {
       ProfScope ps(E.P->ctx, E.st, "inner_solve", 0.0, 0.0);
       build_shifted(U.a1.as<double>(), nullptr, m, U.cap, sh, nr, 0, mats.as<double>(), E.st);
-      small_lu_solve(mats.as<double>(), gbuf.as<double>(), m, nr, E.st);  // y[n][i]
+      small_lu_solve_cm(mats.as<double>(), gbuf.as<double>(), m, nr, E.st);  // y[n][i] (symmetric systems)
     }
     combo(U.V(0), N, m, gbuf.as<double>(), 1, m, nr, N, 1.0, 0.0, sol.as<double>(), N, E.st);
     combo(U.P1(0), N, m, gbuf.as<double>(), 1, m, nr, N, 1.0, 0.0, tuy.as<double>(), N, E.st);
@@ -438,43 +438,59 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
 
 // Projected pair systems [[t+, -s_b I], [-s_b I, t-]] (y_b; y'_b) = (g1_b; g2_b)
 // for b < nb; g (rows of length 2m: g1 then g2) is overwritten by (y; y').
-// With t- = L L^T positive definite the second block is eliminated:
-//   (t+ - s^2 W) y = g1 + s W g2,  y' = W (g2 + s y),  W = t-^{-1} = G^T G, G = L^{-1},
-// so every right-hand side needs one m x m solve (one Cholesky and one
-// triangular inverse shared by all of them).  If t- is not positive definite
-// the full 2m x 2m systems are solved instead.
-void solve_pair_systems(Eng& E, Basis& U, int m, const double* sh, int nb, double* g, DevBuf& mats, DevBuf& work) {
-  const int d = 2 * m;
+// For s_b != 0 the second block is eliminated by multiplying the first
+// equation with t-:
+//   (t- t+ - s^2 I) y = t- g1 + s g2,   y' = (t+ y - g1) / s,
+// one m x m system per right-hand side and no factorisation of t- at all;
+// for s_b = 0 the two blocks decouple (t+ y = g1, t- y' = g2).  The systems
+// are solved by Gaussian elimination with partial pivoting.
+void solve_pair_systems(Eng& E, Basis& U, int m, const std::vector<double>& sh_host, int nb, double* g,
+                        DevBuf& mats, DevBuf& work) {
   ProfScope ps(E.P->ctx, E.st, "inner_solve", 0.0, 0.0);
-  work.ensure(sizeof(double) * ((size_t)3 * m * m + (size_t)2 * nb * m + 8));
-  double* L = work.as<double>();
-  double* G = L + (size_t)m * m;
-  double* W = G + (size_t)m * m;
-  double* tmp = W + (size_t)m * m;  // nb x m
-  double* rhs = tmp + (size_t)nb * m;  // nb x m
-  int* info = reinterpret_cast<int*>(rhs + (size_t)nb * m);
-  copy_block(U.a2.as<double>(), U.cap, m, m, L, m, E.st);
-  small_chol(L, m, m, info, E.st);
-  int inf = 0;
-  E.d2h(&inf, info, sizeof(int));
-  if (inf != 0) {
-    mats.ensure(sizeof(double) * (size_t)nb * d * d);
-    build_shifted(U.a1.as<double>(), U.a2.as<double>(), m, U.cap, sh, nb, 1, mats.as<double>(), E.st);
-    small_lu_solve(mats.as<double>(), g, d, nb, E.st);
-    return;
+  std::vector<int> sb, st;
+  std::vector<double> ss;
+  for (int b = 0; b < nb; ++b) {
+    if (sh_host[b] != 0.0) {
+      sb.push_back(b);
+      st.push_back(0);
+      ss.push_back(sh_host[b]);
+    } else {
+      sb.push_back(b);
+      st.push_back(1);
+      ss.push_back(0.0);
+      sb.push_back(b);
+      st.push_back(2);
+      ss.push_back(0.0);
+    }
   }
-  small_trinv_lower(L, m, m, G, m, E.st);
-  small_gemm(1, 0, m, m, m, 1.0, G, m, G, m, 0.0, W, m, E.st);
-  // tmp = g2 W ; rhs = g1 + s tmp
-  small_gemm(0, 0, nb, m, m, 1.0, g + m, d, W, m, 0.0, tmp, m, E.st);
-  rows_axpy(g, d, tmp, m, sh, nb, m, rhs, m, E.st);
-  mats.ensure(sizeof(double) * (size_t)nb * m * m);
-  build_schur(U.a1.as<double>(), U.cap, W, m, m, sh, nb, mats.as<double>(), E.st);
-  small_lu_solve(mats.as<double>(), rhs, m, nb, E.st);  // rhs <- y
-  // y' = (g2 + s y) W
-  rows_axpy(g + m, d, rhs, m, sh, nb, m, tmp, m, E.st);
-  small_gemm(0, 0, nb, m, m, 1.0, tmp, m, W, m, 0.0, g + m, d, E.st);
-  copy_block(rhs, m, nb, m, g, d, E.st);
+  const int nsys = (int)sb.size();
+  // system table on the device: b, type (ints) then shifts (doubles)
+  std::vector<double> table((size_t)3 * nsys);
+  for (int q = 0; q < nsys; ++q) {
+    table[q] = ss[q];
+    reinterpret_cast<int*>(table.data() + nsys)[q] = sb[q];
+    reinterpret_cast<int*>(table.data() + nsys)[nsys + q] = st[q];
+  }
+  work.ensure(sizeof(double) * ((size_t)m * m + (size_t)3 * nsys * m + (size_t)nb * m + table.size() + 8));
+  double* P = work.as<double>();                // t- t+ (row-major, m x m)
+  double* rhs = P + (size_t)m * m;               // nsys x m
+  double* yt = rhs + (size_t)nsys * m;           // nsys x m
+  double* tg = yt + (size_t)nsys * m;            // nb x m: rows g1_b t-
+  double* tab = tg + (size_t)nb * m;
+  E.h2d(tab, table.data(), sizeof(double) * table.size());
+  const double* sys_shift = tab;
+  const int* sys_b = reinterpret_cast<const int*>(tab + nsys);
+  const int* sys_type = sys_b + nsys;
+  const double* tp = U.a1.as<double>();
+  const double* tm = U.a2.as<double>();
+  small_gemm(0, 0, m, m, m, 1.0, tm, U.cap, tp, U.cap, 0.0, P, m, E.st);
+  small_gemm(0, 0, nb, m, m, 1.0, g, 2 * m, tm, U.cap, 0.0, tg, m, E.st);  // g1_b^T t- (t- symmetric)
+  mats.ensure(sizeof(double) * (size_t)nsys * m * m);
+  pair_systems_build(P, tp, tm, U.cap, m, sys_b, sys_type, sys_shift, nsys, g, 2 * m, tg, mats.as<double>(), rhs,
+                     E.st);
+  small_lu_solve_cm(mats.as<double>(), rhs, m, nsys, E.st);  // rhs <- solutions
+  small_gemm(0, 0, nsys, m, m, 1.0, rhs, m, tp, U.cap, 0.0, yt, m, E.st);  // y^T t+ (t+ symmetric)
+  pair_systems_unpack(g, 2 * m, rhs, yt, sys_b, sys_type, sys_shift, nsys, m, E.st);
 }
 
 // Solve [[T+, -s_n], [-s_n, T-]] (d1; d2) = (r1; r2) approximately.
@@ -539,7 +555,7 @@ InnerResult inner_pair(Eng& E, int prec, const double* r1, const double* r2, int
       gram(h1.as<double>(), N, nr, U.V(0), N, m, N, gbuf.as<double>(), d, rs, E.st);
       gram(h2.as<double>(), N, nr, U.V(0), N, m, N, gbuf.as<double>() + m, d, rs, E.st);
     }
-    solve_pair_systems(E, U, m, sh, nr, gbuf.as<double>(), mats, schur);
+    solve_pair_systems(E, U, m, sh_host, nr, gbuf.as<double>(), mats, schur);
     const double* y1 = gbuf.as<double>();
     const double* y2 = gbuf.as<double>() + m;
     combo(U.V(0), N, m, y1, 1, d, nr, N, 1.0, 0.0, s1.as<double>(), N, E.st);
@@ -1155,7 +1171,7 @@ rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, con
     for (int c = 0; c < npair; ++c)
       RID_HIP(hipMemsetAsync(g.as<double>() + (long)c * d + m, 0, sizeof(double) * m, E.st));
     build_shifted(B.a1.as<double>(), B.a2.as<double>(), m, B.cap, shdev, npair, 1, mats.as<double>(), E.st);
-    small_lu_solve(mats.as<double>(), g.as<double>(), d, npair, E.st);
+    small_lu_solve_cm(mats.as<double>(), g.as<double>(), d, npair, E.st);  // symmetric systems
     const double* y = g.as<double>();
     const double* yp = g.as<double>() + m;
     combo(B.V(0), N, m, y, 1, d, npair, N, 1.0, 0.0, uu.as<double>(), N, E.st);

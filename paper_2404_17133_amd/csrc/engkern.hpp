@@ -76,6 +76,16 @@ void small_chol(double* a, int m, int lda, int* info, hipStream_t s);
 // and g_b at rhs + b * m (overwritten by y_b).  A pivot below 1e-300 in
 // magnitude is replaced by +-1e-300.
 void small_lu_solve(double* mats, double* rhs, int m, int nb, hipStream_t s);
+// The same for column-major matrices (faster: two barriers per column).
+void small_lu_solve_cm(double* mats, double* rhs, int m, int nb, hipStream_t s);
+// Pair systems of the inner full-TDDFT solve (see dense.hip): build the
+// nsys column-major matrices and right-hand sides, and write the solutions
+// back into g (rows of length 2m: y then y').
+void pair_systems_build(const double* P, const double* tp, const double* tm, int ld, int m, const int* sys_b,
+                        const int* sys_type, const double* sys_shift, int nsys, const double* g, int ldg,
+                        const double* tg, double* mats, double* rhs, hipStream_t s);
+void pair_systems_unpack(double* g, int ldg, const double* sol, const double* yt, const int* sys_b,
+                         const int* sys_type, const double* sys_shift, int nsys, int m, hipStream_t s);
 // C (m x n) = alpha * op(A) op(B) + beta * C, row-major, op = transpose if t*.
 void small_gemm(int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
                 double beta, double* C, int ldc, hipStream_t s);

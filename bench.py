@@ -283,6 +283,63 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+SWEEP = [
+    # label, preconditioner, Naux_ris (None: config value), exchange rows (None: Naux_ris/9), source, noise, window
+    ("diagonal", "diag", None, None, "svd", 0.05, True),
+    ("rid (s,s): J and K on the s rows", "ris", "s", "s", "svd", 0.05, True),
+    ("rid (d,s): J on all rows, K on the s rows", "ris", None, None, "svd", 0.05, True),
+    ("rid (d,d): J and K on all rows", "ris", None, "all", "svd", 0.05, True),
+    ("rid (d,s), twice the auxiliary rows", "ris", "x2", None, "svd", 0.05, True),
+    ("full auxiliary basis, 5% noise, window", "ris", "full", "all", "full", 0.05, True),
+    ("exact model: T = A (no noise, no window)", "ris", "full", "all", "full", 0.0, False),
+]
+
+
+def bench_sweep(args):
+    """Preconditioner richness sweep (Sec. 3.2, Fig. 2 analogue) on the
+    no=100 workload: iterations and products of the full-TDDFT solve for the
+    ris model with more or fewer auxiliary rows in its Coulomb (J) and
+    exchange (K) parts, up to the exact model T = A; the roots are checked
+    against the stored FP64 oracle results."""
+    import numpy as np
+    import torch
+
+    import paper_2404_17133_amd as rid
+    from synth import config_sizes, make_problem
+
+    no, nv, naux, nris, seed = config_sizes("c1")
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_c1.json")))
+    ref = np.array(gold["rpa_omega"])
+    k = gold["k"]
+    rows = []
+    for label, pc, nr, nk, src, noise, window in SWEEP:
+        n_ris = {None: nris, "s": int(round(nris / 9)), "x2": 2 * nris, "full": naux}[nr]
+        n_k = {None: None, "s": int(round(nris / 9)), "all": n_ris}[nk]
+        kw = {} if window else {"t_cut": float("inf")}
+        p = make_problem(no, nv, naux, n_ris, naux_ris_k=n_k, seed=seed, device="cuda:0", ris_source=src,
+                         noise=noise, **kw)
+        ctx = rid.Context(0)
+        prob = rid.Problem.from_synth(ctx, p)
+        prob.eigen(k, "rpa", pc, "mixed", vectors=False)  # warm (tuning, casts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = prob.eigen(k, "rpa", pc, "mixed", vectors=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = out["stats"]
+        rows.append({"preconditioner": label, "naux_ris_j": n_ris if pc == "ris" else 0,
+                     "naux_ris_k": p.naux_ris_k if pc == "ris" else 0, "status": out["status"],
+                     "n_iter": st["n_iter"], "n_mv": st["n_mv"], "n_inner_mv": st["n_inner_mv"],
+                     "seconds": round(el, 3), "max_abs_omega_err_Ha": float(np.abs(out["omega"] - ref).max())})
+        log("%-45s iters %3d  products %4d  inner %5d  %.2f s  err %.1e" % (
+            label, st["n_iter"], st["n_mv"], st["n_inner_mv"], el, rows[-1]["max_abs_omega_err_Ha"]))
+        ctx.close()
+        del p, prob
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "preconditioner sweep: full TDDFT, 10 roots, no=100 nv=400 Naux=2000, mixed "
+                                  "precision, tolerance 1e-5", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,9 +352,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy (x * 1.0 on float32) run before timing, so that "
                          "hardware-counter runs can calibrate byte counters against a known size")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve", "sweep"],
                     help="single: one no=200 molecule (default); batch: many molecules in one batched "
-                         "solve; serve: a request stream through the server")
+                         "solve; serve: a request stream through the server; sweep: ris-model richness "
+                         "sweep on the no=100 molecule")
     ap.add_argument("--molecules", type=int, default=64, help="batch: number of molecules")
     ap.add_argument("--sequential", action="store_true", help="batch: also solve the molecules one by one")
     ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
@@ -306,7 +364,7 @@ def main():
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent requests")
     ap.add_argument("--hbm-budget-gb", type=int, default=96, help="serve: admission budget")
     args = ap.parse_args()
-    if args.workload != "single":
+    if args.workload in ("batch", "serve"):
         # many concurrent solve streams: more hardware queues keep them from
         # queueing behind each other (set before the HIP runtime starts)
         os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
@@ -317,6 +375,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import numpy as np
     import torch

@@ -659,6 +659,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         if (!J.exch || c >= J.nchunks) continue;
         const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
         OpWork& w = *J.j->work;
+        // one product per P, run back to back per workgroup (Xt shared)
         GemmParams g{};
         g.A = J.ov.b_ij + (long)c0 * J.no * J.no + (long)J.i0 * J.no + J.i0;
         g.B = w.xt.p;
@@ -666,20 +667,21 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.M = J.no_a;
         g.N = J.nvec * J.nv_a;
         g.K = J.no_a;
-        g.np = 1;
+        g.np = pcc;
         g.pps = 1;
         g.nz2 = 1;
         g.lda = J.no;
         g.ldb = J.no_a;
         g.ldc = (long)J.nvec * J.nv_a;
-        g.sA1 = (long)J.no * J.no;
-        g.sC1 = J.s_per_p;
+        g.sAp = (long)J.no * J.no;
+        g.sBp = 0;
+        g.sCs = J.s_per_p;
         g.alpha = 1.0;
-        g.mode = GEMM_STORE;
-        g.order = ORDER_ZIN;  // each XCD keeps its share of Xt in L2 across the batch of P
+        g.mode = GEMM_STORE_EACH;
+        g.order = ORDER_ZIN;  // each XCD keeps its share of Xt in L2 across all P
         ps.flops += 2.0 * J.no_a * (double)J.nvec * J.nv_a * J.no_a * pcc;
         ps.bytes += esz * ((double)pcc * J.no_a * J.no_a + (double)J.nvec * J.nv_a * J.no_a + (double)pcc * J.s_per_p);
-        plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.nv_a, pcc, 1, J.no_a, false, st);
+        plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.nv_a, 1, pcc, J.no_a, true, st);
       }
       stage.launch(ctx, GF_EXCH_S, st);
     }
@@ -735,20 +737,21 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.M = J.no_a;
         g.N = J.nvec * J.no_a;
         g.K = J.nv_a;
-        g.np = 1;
+        g.np = pcc;
         g.pps = 1;
         g.nz2 = 1;
         g.lda = J.nv;
         g.ldb = J.nv_a;
         g.ldc = (long)J.nvec * J.no_a;
-        g.sA1 = J.n;
-        g.sC1 = J.q_per_p;
+        g.sAp = J.n;
+        g.sBp = 0;
+        g.sCs = J.q_per_p;
         g.alpha = 1.0;
-        g.mode = GEMM_STORE;
+        g.mode = GEMM_STORE_EACH;
         g.order = ORDER_ZIN;
         ps.flops += 2.0 * J.no_a * (double)J.nvec * J.no_a * J.nv_a * pcc;
         ps.bytes += esz * ((double)pcc * J.no_a * J.nv_a + (double)J.nvec * J.no_a * J.nv_a + (double)pcc * J.q_per_p);
-        plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, pcc, 1, J.nv_a, false, st);
+        plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, 1, pcc, J.nv_a, true, st);
       }
       stage.launch(ctx, GF_EXCH_Q, st);
     }

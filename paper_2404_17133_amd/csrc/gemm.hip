@@ -247,25 +247,10 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
         for (int j = 0; j < ANN; ++j) acc[i][j] = At::mma(At::op(fa[i], s), At::op(fb[j], s), acc[i][j]);
   };
 
-  // One stage in flight: the next stage's global loads are issued before the
-  // MFMAs of the current stage and written to the other LDS buffer after them.
-  uint4 pa[CPT];
-  if (nstage > 0) {
-    gload(0, pa);
-    lstore(0, pa);
-  }
-  __syncthreads();
-  for (int t = 0; t < nstage; ++t) {
-    if (t + 1 < nstage) gload(t + 1, pa);
-    compute(t & 1);
-    if (t + 1 < nstage) lstore((t + 1) & 1, pa);
-    __syncthreads();
-  }
-
-  // epilogue
   const acc_t alpha = (acc_t)p.alpha;
-  if (p.mode == GEMM_STORE) {
-    E_t* C = reinterpret_cast<E_t*>(p.C) + z1 * p.sC1 + z2 * p.sC2;
+  // store the tile in the element type at C (used per batch by
+  // GEMM_STORE_EACH and once by GEMM_STORE)
+  auto store_tile = [&](E_t* C) {
 #pragma unroll
     for (int i = 0; i < AMN; ++i)
 #pragma unroll
@@ -276,6 +261,45 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
           const int n = n0 + wn + j * At::AM + lr;
           if (m < p.M && n < p.N) C[(long)m * p.ldc + n] = At::out(alpha * acc[i][j][r]);
         }
+  };
+  const bool each = p.mode == GEMM_STORE_EACH;
+  E_t* Ce = reinterpret_cast<E_t*>(p.C) + z1 * p.sC1 + z2 * p.sC2;
+
+  // One stage in flight: the next stage's global loads are issued before the
+  // MFMAs of the current stage and written to the other LDS buffer after them.
+  // In GEMM_STORE_EACH mode the batches of the split run back to back through
+  // the same pipeline, the tile of each batch being stored when its last
+  // stage is done, so that the next batch's first stage is already loaded.
+  uint4 pa[CPT];
+  if (nstage > 0) {
+    gload(0, pa);
+    lstore(0, pa);
+  }
+  __syncthreads();
+  int kt_c = 0, p_c = pbeg;  // stage within its batch, and batch, of the stage being computed
+  for (int t = 0; t < nstage; ++t) {
+    if (t + 1 < nstage) gload(t + 1, pa);
+    compute(t & 1);
+    if (each && ++kt_c == nkt) {
+      store_tile(Ce + (long)p_c * p.sCs);
+#pragma unroll
+      for (int i = 0; i < AMN; ++i)
+#pragma unroll
+        for (int j = 0; j < ANN; ++j)
+#pragma unroll
+          for (int r = 0; r < At::NACC; ++r) acc[i][j][r] = acc_t(0);
+      kt_c = 0;
+      ++p_c;
+    }
+    if (t + 1 < nstage) lstore((t + 1) & 1, pa);
+    __syncthreads();
+  }
+
+  // epilogue
+  if (each) {
+    return;
+  } else if (p.mode == GEMM_STORE) {
+    store_tile(Ce);
   } else {
     acc_t* C = reinterpret_cast<acc_t*>(p.C) + split * p.sCs + z1 * p.sC1 + z2 * p.sC2;
     const bool add = p.mode == GEMM_PARTIAL_ADD;
@@ -312,15 +336,15 @@ struct TileCoord {
 };
 
 // Tile coordinates of walk position t (see GemmOrder).
-__device__ inline TileCoord walk_decode(int order, long t, int tiles_m, int tiles_n, int nz) {
+__device__ inline TileCoord walk_decode(int order, long t, int tiles_m, int tiles_n, int nz, int nsplit) {
   TileCoord c;
   if (order == ORDER_ZIN) {
     c.tm = (int)(t % tiles_m);
     long r = t / tiles_m;
     c.z = (int)(r % nz);
     r /= nz;
-    c.tn = (int)(r % tiles_n);
-    c.split = (int)(r / tiles_n);
+    c.split = (int)(r % nsplit);
+    c.tn = (int)(r / nsplit);
     return c;
   }
   const long tiles = (long)tiles_m * tiles_n;
@@ -338,14 +362,15 @@ template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
 __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmParams p, int nz, long total) {
   const int tiles_m = (p.M + BM - 1) / BM;
   const int tiles_n = (p.N + BN - 1) / BN;
-  const TileCoord c = walk_decode(p.order, xcd_walk(blockIdx.x, total), tiles_m, tiles_n, nz);
+  const int nsplit = (int)(total / ((long)tiles_m * tiles_n * nz));
+  const TileCoord c = walk_decode(p.order, xcd_walk(blockIdx.x, total), tiles_m, tiles_n, nz, nsplit);
   gemm_tile<T, BM, BN, WM, WN, VEC>(p, c.tm, c.tn, c.z, c.split);
 }
 
 // Device descriptor of one member of a grouped launch.
 struct GroupDesc {
   GemmParams p;
-  int tiles_m, tiles_n, nz, pad;
+  int tiles_m, tiles_n, nz, nsplit;
   long begin;  // index of the member's first tile in the launch
 };
 
@@ -368,7 +393,8 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_grouped_kernel(
         hi = mid - 1;
     }
     const GemmParams p = gd[lo].p;
-    const TileCoord c = walk_decode(p.order, t - gd[lo].begin, gd[lo].tiles_m, gd[lo].tiles_n, gd[lo].nz);
+    const TileCoord c =
+        walk_decode(p.order, t - gd[lo].begin, gd[lo].tiles_m, gd[lo].tiles_n, gd[lo].nz, gd[lo].nsplit);
     gemm_tile<T, BM, BN, WM, WN, VEC>(p, c.tm, c.tn, c.z, c.split);
   }
 }
@@ -456,6 +482,7 @@ bool vec_ok(const GemmParams& p) {
 void check_params(const GemmParams& p, int nz, int nsplit) {
   RID_CHECK(p.np >= 1 && p.pps >= 1 && p.nz2 >= 1, RID_ERR_INTERNAL, "gemm: bad batch counts");
   RID_CHECK(p.order >= ORDER_MN && p.order <= ORDER_ZIN, RID_ERR_INTERNAL, "gemm: bad tile order");
+  RID_CHECK(p.mode >= GEMM_STORE && p.mode <= GEMM_STORE_EACH, RID_ERR_INTERNAL, "gemm: bad mode");
   RID_CHECK((long)nsplit * p.pps >= p.np, RID_ERR_INTERNAL, "gemm: splits do not cover batches");
   RID_CHECK(ceil_div_l(p.M, 64) * ceil_div_l(p.N, 64) < (1L << 31), RID_ERR_SHAPE, "gemm: grid too large");
   RID_CHECK(nz < 65536 && nsplit < 65536, RID_ERR_SHAPE, "gemm: batch grid too large");
@@ -485,7 +512,7 @@ void gemm_grouped(const GemmGroup* mem, int n, int cfg, int family, void* desc_d
       d.tiles_m = ceil_div(p.M, bm);
       d.tiles_n = ceil_div(p.N, bn);
       d.nz = mem[i].nz;
-      d.pad = 0;
+      d.nsplit = mem[i].nsplit;
       d.begin = total[pass];
       total[pass] += (long)d.tiles_m * d.tiles_n * mem[i].nz * mem[i].nsplit;
       ++cnt[pass];

@@ -14,7 +14,14 @@
 
 namespace rid {
 
-enum GemmMode { GEMM_STORE = 0, GEMM_PARTIAL_SET = 1, GEMM_PARTIAL_ADD = 2 };
+// GEMM_STORE: C[z] = alpha * (sum over all batches), in the element type.
+// GEMM_PARTIAL_SET / _ADD: each split writes (adds) its partial sum, in the
+// accumulator type, at C + split * sCs.
+// GEMM_STORE_EACH: no reduction; every batch p is its own product, stored in
+// the element type at C + p * sCs.  A workgroup runs the pps batches of its
+// split back to back through one pipeline (the operand that does not change
+// with p has batch stride 0).
+enum GemmMode { GEMM_STORE = 0, GEMM_PARTIAL_SET = 1, GEMM_PARTIAL_ADD = 2, GEMM_STORE_EACH = 3 };
 
 // Contraction family of a launch.  Each family gets its own kernel symbol
 // (same code) so that profilers report the families separately.
@@ -43,8 +50,8 @@ struct GemmParams {
 // share in that XCD's L2.
 //   ORDER_MN: tm fastest, then tn, batch, split (B row block reused);
 //   ORDER_NM: tn fastest, then tm, batch, split (A row block reused);
-//   ORDER_ZIN: tm fastest, then batch, then tn, split (B row block reused
-//              across all batches).
+//   ORDER_ZIN: tm fastest, then batch, then split, then tn (B row block
+//              reused across all batches and splits).
 enum GemmOrder { ORDER_MN = 0, ORDER_NM = 1, ORDER_ZIN = 2 };
 
 // Element-type tag for bf16 operands stored as raw uint16_t.

@@ -638,7 +638,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       w.jbuf.ensure(sizeof(double) * J.nvec * J.n);
       coul_bwd<E>(w.t64.as<double>(), J.ov.b_ia, J.naux_j, J.n, J.nvec, w.jbuf.as<double>(), st);
       ps.flops += 2.0 * J.nvec * J.naux_j * (double)J.n;
-      ps.bytes += esz * (double)J.naux_j * J.n * ceil_div(J.nvec, 8) + 8.0 * J.nvec * J.n;
+      ps.bytes += esz * (double)J.naux_j * J.n * (J.nvec <= 16 ? 1 : ceil_div(J.nvec, 24)) + 8.0 * J.nvec * J.n;
     }
   }
 

@@ -68,6 +68,8 @@ __global__ __launch_bounds__(256) void coul_bwd_kernel(const double* __restrict_
 #pragma unroll
   for (int q = 0; q < NVB; ++q) acc[q] = 0.0;
   if (ia < n) {
+    // several rows of b in flight per thread: the loop is latency-bound
+#pragma unroll 8
     for (int p = 0; p < naux; ++p) {
       const double bv = from_elem<E>(b[(long)p * n + ia]);
 #pragma unroll
@@ -172,9 +174,16 @@ void reduce_splits(const A* part, int ns, long stride, long n, double* out, hipS
 template <typename E>
 void coul_bwd(const double* t, const E* b, int naux, long n, int nvec, double* j, hipStream_t s) {
   if (n == 0 || nvec == 0) return;
-  constexpr int NVB = 8;
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ceil_div(nvec, NVB));
-  hipLaunchKernelGGL((coul_bwd_kernel<E, NVB>), grid, dim3(256), 0, s, t, b, naux, n, nvec, j);
+  // one pass over b per group of vectors: as few passes as the register
+  // budget allows (b is the bulk of the traffic)
+  const unsigned gx = (unsigned)((n + 255) / 256);
+  if (nvec <= 8)
+    hipLaunchKernelGGL((coul_bwd_kernel<E, 8>), dim3(gx, 1), dim3(256), 0, s, t, b, naux, n, nvec, j);
+  else if (nvec <= 16)
+    hipLaunchKernelGGL((coul_bwd_kernel<E, 16>), dim3(gx, 1), dim3(256), 0, s, t, b, naux, n, nvec, j);
+  else
+    hipLaunchKernelGGL((coul_bwd_kernel<E, 24>), dim3(gx, (unsigned)ceil_div(nvec, 24)), dim3(256), 0, s, t, b, naux,
+                       n, nvec, j);
   RID_HIP(hipGetLastError());
 }
 

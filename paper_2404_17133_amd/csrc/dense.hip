@@ -543,12 +543,14 @@ __global__ __launch_bounds__(DB) void lu_solve_kernel(double* mats, double* rhs,
 // The pivot search of column j + 1 visits exactly the rows each thread
 // updated at column j, so no barrier separates the two.
 constexpr int LB = 256;
+constexpr int LU_MAX = 2048;  // largest system of lu_cm_kernel (pivot row staged in LDS)
 
 __device__ inline double guard_pivot(double p) { return fabs(p) < 1e-300 ? (p < 0.0 ? -1e-300 : 1e-300) : p; }
 
 __global__ __launch_bounds__(LB) void lu_cm_kernel(double* mats, double* rhs, int m) {
   __shared__ double rv[LB / 64];
   __shared__ int ri[LB / 64];
+  __shared__ double prow[LU_MAX];
   double* a = mats + (long)blockIdx.x * m * m;
   double* g = rhs + (long)blockIdx.x * m;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -597,12 +599,30 @@ __global__ __launch_bounds__(LB) void lu_cm_kernel(double* mats, double* rhs, in
       }
     }
     __syncthreads();
+    // the pivot row right of the diagonal, staged in LDS once for all rows
+    // (read from memory for systems larger than the staging buffer)
+    const bool staged = m <= LU_MAX;
+    if (staged)
+      for (int k = j + 1 + tid; k < m; k += LB) prow[k] = a[(long)k * m + j];
     const double pv = guard_pivot(a[(long)j * m + j]);
     const double gj = g[j];
+    __syncthreads();
     for (int i = j + 1 + tid; i < m; i += LB) {
       const double l = a[(long)j * m + i] / pv;
       a[(long)j * m + i] = l;
-      for (int k = j + 1; k < m; ++k) a[(long)k * m + i] -= l * a[(long)k * m + j];
+      // eight independent loads in flight per step of the row update
+      int k = j + 1;
+      for (; k + 8 <= m; k += 8) {
+        double v[8], u[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          v[q] = a[(long)(k + q) * m + i];
+          u[q] = staged ? prow[k + q] : a[(long)(k + q) * m + j];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[(long)(k + q) * m + i] = v[q] - l * u[q];
+      }
+      for (; k < m; ++k) a[(long)k * m + i] -= l * (staged ? prow[k] : a[(long)k * m + j]);
       g[i] -= l * gj;
     }
   }

@@ -99,10 +99,15 @@ def measured_traffic(family: str, dtype: str):
         return None
     t = {"f32": "float", "bf16": "bf16_t", "f64": "double"}[dtype]
     fam = family[4:] if family.startswith("ris_") else family
+    # dispatch-weighted mean over the tile shapes the autotuner picked
+    n_tot, b_tot = 0, 0.0
     for line in text.splitlines():
-        if line.startswith("| gemm_nt<%s,128x128," % t) and line.split("|")[1].strip().endswith("[%s]" % fam):
-            return float(line.split("|")[5]) * 1e9
-    return None
+        cells = [c.strip() for c in line.split("|")]
+        if len(cells) > 5 and cells[1].startswith("gemm_nt<%s," % t) and cells[1].endswith("[%s]" % fam):
+            n = int(cells[2])
+            n_tot += n
+            b_tot += n * float(cells[5]) * 1e9
+    return b_tot / n_tot if n_tot else None
 
 
 def f32_problem(rid, ctx, d, dipoles=False):

@@ -341,8 +341,36 @@ def bench_sweep(args):
         ctx.close()
         del p, prob
         torch.cuda.empty_cache()
+    # warm start (NEXT-2): the X, Y of the default problem seed the solve on a
+    # neighbour (every tensor perturbed by 1 %, as after a geometry step)
+    from synth import related_problem
+    p1 = make_problem(no, nv, naux, nris, seed=seed, device="cuda:0")
+    p2 = related_problem(p1, step=0.01)
+    ctx = rid.Context(0)
+    g1, g2 = rid.Problem.from_synth(ctx, p1), rid.Problem.from_synth(ctx, p2)
+    first = g1.eigen(k, "rpa", "ris", "mixed")
+    guess = torch.cat([first["x"], first["y"]]).contiguous()
+    g2.eigen(k, "rpa", "ris", "mixed", vectors=False)  # warm-up of the new shapes
+    warm_rows = {}
+    for name, kw in (("cold", {}), ("warm", {"guess": guess})):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = g2.eigen(k, "rpa", "ris", "mixed", vectors=False, **kw)
+        torch.cuda.synchronize()
+        warm_rows[name] = {"status": out["status"], "n_iter": out["stats"]["n_iter"], "n_mv": out["stats"]["n_mv"],
+                           "n_inner_mv": out["stats"]["n_inner_mv"], "seconds": round(time.perf_counter() - t0, 3),
+                           "omega": out["omega"]}
+        log("%s start on the neighbour: iters %d products %d  %.2f s" % (
+            name, out["stats"]["n_iter"], out["stats"]["n_mv"], warm_rows[name]["seconds"]))
+    diff = float(np.abs(warm_rows["warm"]["omega"] - warm_rows["cold"]["omega"]).max())
+    for v in warm_rows.values():
+        v.pop("omega")
+    ctx.close()
     print(json.dumps({"workload": "preconditioner sweep: full TDDFT, 10 roots, no=100 nv=400 Naux=2000, mixed "
-                                  "precision, tolerance 1e-5", "rows": rows}), flush=True)
+                                  "precision, tolerance 1e-5", "rows": rows,
+                      "warm_start": {"neighbour": "every tensor x (1 + 0.01 Z), energies moved by 0.001 U[-1,1]",
+                                     "cold": warm_rows["cold"], "warm": warm_rows["warm"],
+                                     "max_abs_omega_diff_Ha": diff}}), flush=True)
 
 
 def main():

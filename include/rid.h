@@ -141,6 +141,14 @@ typedef struct {
   double init_tol;       /* ris initial-guess threshold (1e-3, Sec. 3.1) */
   int32_t init_max_iter; /* ris initial-guess iterations (20) */
   int32_t m_max;         /* subspace cap before restart, 0 = max(200, 40 k) */
+  /* Warm start (eigen-solves): n_guess device vectors (n_guess x N, FP64,
+   * row-major, caller-owned, read during the call) that span a start
+   * subspace, e.g. the X (and Y) of a solve on a related problem.  When
+   * given they replace the Sec. 3.2 initial guess (no ris guess solve); the
+   * N_init unit vectors of the smallest de are appended and the set is
+   * orthonormalised (dependent directions dropped).  NULL / 0: none. */
+  const double* guess_dev;
+  int32_t n_guess;
 } rid_solve_opts;
 
 #define RID_MAX_HISTORY 128
@@ -256,6 +264,8 @@ typedef struct {
   const double* p_dev;     /* nrhs x N */
   const double* omega_host;/* nfreq */
   rid_solve_opts opts;
+  double* x_dev;           /* eigen: optional output X (k x N, device, caller-owned) or NULL */
+  double* y_dev;           /* eigen RPA: optional output Y (k x N) or NULL */
 } rid_request;
 
 typedef struct {

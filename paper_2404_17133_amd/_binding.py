@@ -65,7 +65,7 @@ class rid_solve_opts(ctypes.Structure):
         ("precond", ctypes.c_int32), ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
         ("max_iter", ctypes.c_int32), ("n_extra_init", ctypes.c_int32), ("inner_tol", ctypes.c_double),
         ("inner_max_iter", ctypes.c_int32), ("init_tol", ctypes.c_double), ("init_max_iter", ctypes.c_int32),
-        ("m_max", ctypes.c_int32),
+        ("m_max", ctypes.c_int32), ("guess_dev", ctypes.c_void_p), ("n_guess", ctypes.c_int32),
     ]
 
 
@@ -98,7 +98,7 @@ class rid_request(ctypes.Structure):
         ("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("nrhs", ctypes.c_int32), ("nfreq", ctypes.c_int32),
         ("p_dev", ctypes.c_void_p), ("omega_host", ctypes.POINTER(ctypes.c_double)),
-        ("opts", rid_solve_opts),
+        ("opts", rid_solve_opts), ("x_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p),
     ]
 
 

@@ -101,6 +101,8 @@ void rid_solve_opts_default(rid_solve_opts* o) {
   o->init_tol = 1e-3;
   o->init_max_iter = 20;
   o->m_max = 0;
+  o->guess_dev = nullptr;
+  o->n_guess = 0;
 }
 
 rid_status rid_context_create(int32_t device, void* hip_stream, const rid_allocator* alloc, rid_context** out) {

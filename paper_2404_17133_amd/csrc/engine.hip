@@ -908,6 +908,9 @@ void validate_opts(const rid_solve_opts& o, const rid_problem* P) {
   RID_CHECK(o.m_max >= 0 && o.m_max <= 1000, RID_ERR_INVALID_ARG, "m_max must be in [0, 1000]");
   if (o.precond == RID_PRECOND_RIS)
     RID_CHECK(P->has_ris(), RID_ERR_INVALID_ARG, "ris preconditioner needs a ris tensor");
+  RID_CHECK(o.n_guess >= 0 && (o.n_guess == 0 || o.guess_dev != nullptr), RID_ERR_INVALID_ARG,
+            "n_guess must be >= 0, with guess_dev when > 0");
+  RID_CHECK((long)o.n_guess <= 4 * P->n(), RID_ERR_SHAPE, "too many guess vectors");
   if (o.precision == RID_PRECISION_FP64) {
     RID_CHECK(P->b_dt == RID_F64, RID_ERR_DTYPE, "an FP64 solve needs FP64 tensors");
     if (o.precond == RID_PRECOND_RIS)
@@ -934,7 +937,16 @@ rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode,
   EigCore core;
   auto tp = Clock::now();
   int n0 = n_init;
-  if (mode == RID_TDA) {
+  if (o.n_guess > 0) {
+    // warm start: the caller's vectors, then the unit vectors of the
+    // smallest de; dependent directions are dropped when the basis is built
+    n0 = o.n_guess + n_init;
+    v0.ensure(sizeof(double) * (size_t)n0 * N);
+    RID_HIP(hipMemcpyAsync(v0.p, o.guess_dev, sizeof(double) * (size_t)o.n_guess * N, hipMemcpyDeviceToDevice,
+                           E.st));
+    const int* pos = E.put_ints(posd, smallest_positions(P, n_init));
+    unit_vectors(pos, n_init, N, v0.as<double>() + (long)o.n_guess * N, N, E.st);
+  } else if (mode == RID_TDA) {
     if (!ris) {
       v0.ensure(sizeof(double) * n_init * N);
       const int* pos = E.put_ints(posd, smallest_positions(P, n_init));

@@ -69,7 +69,8 @@ rid_status run_one(rid_problem* P, const rid_request& r, rid_result* res, const 
   rid_status s;
   try {
     if (r.kind == 0) {
-      s = eigen_solve(P, r.opts, r.k, r.mode, res->omega_host, nullptr, nullptr, res->resid_host, st, ex);
+      s = eigen_solve(P, r.opts, r.k, r.mode, res->omega_host, r.x_dev, r.mode == RID_RPA ? r.y_dev : nullptr,
+                      res->resid_host, st, ex);
     } else {
       s = response_solve(P, r.opts, r.nrhs, r.p_dev, r.nfreq, r.omega_host, res->alpha_host, nullptr,
                          res->resid_host, st, ex);

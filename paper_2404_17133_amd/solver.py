@@ -125,11 +125,18 @@ class Context:
             pass
 
 
-def default_opts(precond: str = "ris", precision: str = "fp64", **kw) -> B.rid_solve_opts:
+def default_opts(precond: str = "ris", precision: str = "fp64", guess: Optional[torch.Tensor] = None,
+                 **kw) -> B.rid_solve_opts:
+    """Solve options.  guess: optional (n, N) float64 device tensor of start
+    vectors (warm start); the caller keeps it alive until the solve ends."""
     o = B.rid_solve_opts()
     B.lib.rid_solve_opts_default(ctypes.byref(o))
     o.precond = _PRECOND[precond]
     o.precision = _PRECISION[precision]
+    if guess is not None:
+        _need_dev(guess, None, "guess")
+        o.guess_dev = guess.data_ptr()
+        o.n_guess = guess.shape[0]
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
@@ -259,12 +266,23 @@ class Problem:
 
 
 def make_request(kind: str, opts: B.rid_solve_opts, k: int = 0, mode: str = "tda",
-                 p: Optional[torch.Tensor] = None, omegas: Optional[np.ndarray] = None):
+                 p: Optional[torch.Tensor] = None, omegas: Optional[np.ndarray] = None,
+                 x_out: Optional[torch.Tensor] = None, y_out: Optional[torch.Tensor] = None):
+    """A batch/server request.  Eigen requests may name device tensors
+    x_out (k, N) and y_out (k, N, full TDDFT) that receive X and Y."""
     r = B.rid_request()
     r.opts = opts
     keep = []
     if kind == "eigen":
         r.kind, r.k, r.mode = 0, k, _MODE[mode]
+        if x_out is not None:
+            _need_dev(x_out, (k, x_out.shape[1]), "x_out")
+            r.x_dev = x_out.data_ptr()
+            keep.append(x_out)
+        if y_out is not None:
+            _need_dev(y_out, (k, y_out.shape[1]), "y_out")
+            r.y_dev = y_out.data_ptr()
+            keep.append(y_out)
     else:
         r.kind = 1
         om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))

@@ -20,4 +20,5 @@ from .generate import (  # noqa: F401
     molecule_sizes,
     batch_member,
     serve_trace,
+    related_problem,
 )

@@ -347,3 +347,25 @@ def serve_trace(n: int, seed: int = 400, no_min: int = 20, no_max: int = 300) ->
             d["omegas"] = sorted(0.3 * float(x) for x in u[5:8])
         out.append(d)
     return out
+
+
+def related_problem(p: Problem, step: float = 0.01, seed: int = 1) -> Problem:
+    """A neighbour of problem p, as after a small geometry step: every
+    three-index tensor multiplied elementwise by (1 + step Z) (Z ~ N(0, 1),
+    mirrored for the ij and ab blocks) and the orbital energies moved by
+    0.1 step U[-1, 1] (kept sorted)."""
+    dev = p.b_ia.device
+    base = 7_000_000 + seed
+
+    def bump(t, stream, symmetric):
+        if t is None:
+            return None
+        return t * (1.0 + step * _normal_tensor(base, stream, tuple(t.shape), dev, symmetric=symmetric))
+
+    eo, _ = torch.sort(p.eps_occ + 0.1 * step * (2.0 * counter_uniforms(base, 1, 0, p.no, dev) - 1.0))
+    ev, _ = torch.sort(p.eps_vir + 0.1 * step * (2.0 * counter_uniforms(base, 2, 0, p.nv, dev) - 1.0))
+    kw = {f.name: getattr(p, f.name) for f in dataclasses.fields(p)}
+    kw.update(eps_occ=eo, eps_vir=ev, b_ia=bump(p.b_ia, 3, False), b_ij=bump(p.b_ij, 4, True),
+              b_ab=bump(p.b_ab, 5, True), bris_ia=bump(p.bris_ia, 6, False), bris_ij=bump(p.bris_ij, 7, True),
+              bris_ab=bump(p.bris_ab, 8, True))
+    return Problem(**kw)

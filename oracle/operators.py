@@ -15,6 +15,11 @@ W'_{ia,jb} = (ib|ja).  The A+B line doubles the Coulomb factor printed in
 Eq. hessian (which reads 2(ia|jb) for A+B); this follows from A = de + 2K
 (restricted singlet) and B = 2K, and agrees with the printed A-B.
 
+Range-separated hybrids (the paper's second functional, wB97X, Sec. 4):
+the exact-exchange integrals become a_x (pq|rs) + b_x (pq|rs)^LR, the
+long-range (attenuated) integrals factored through a second tensor C,
+(pq|rs)^LR = sum_Q C^Q_pq C^Q_rs, so W -> a_x W + b_x W^LR and likewise W'.
+
 The ris model T (Sec. 2.2.2, Eq. TDDFT-ris_approx) has the same structure,
 built from the minimal-auxiliary tensor: the Coulomb part uses all of its
 rows, the exchange part only the leading ``naux_ris_k`` rows (the (d, s)
@@ -47,6 +52,14 @@ class OracleProblem:
     bris_ab: Optional[np.ndarray] = None
     naux_ris_k: int = 0
     t_cut: float = np.inf
+    # range-separated hybrid: weight and long-range tensors (full and ris)
+    b_x: float = 0.0
+    blr_ia: Optional[np.ndarray] = None
+    blr_ij: Optional[np.ndarray] = None
+    blr_ab: Optional[np.ndarray] = None
+    brislr_ia: Optional[np.ndarray] = None
+    brislr_ij: Optional[np.ndarray] = None
+    brislr_ab: Optional[np.ndarray] = None
 
     @classmethod
     def from_arrays(cls, d: dict) -> "OracleProblem":
@@ -56,7 +69,13 @@ class OracleProblem:
                    b_ia=f("b_ia"), b_ij=f("b_ij"), b_ab=f("b_ab"), a_x=float(d["a_x"]),
                    bris_ia=f("bris_ia"), bris_ij=f("bris_ij"), bris_ab=f("bris_ab"),
                    naux_ris_k=int(d.get("naux_ris_k") or 0),
-                   t_cut=float(d.get("t_cut", np.inf)))
+                   t_cut=float(d.get("t_cut", np.inf)),
+                   b_x=float(d.get("b_x") or 0.0), blr_ia=f("blr_ia"), blr_ij=f("blr_ij"), blr_ab=f("blr_ab"),
+                   brislr_ia=f("brislr_ia"), brislr_ij=f("brislr_ij"), brislr_ab=f("brislr_ab"))
+
+    @property
+    def has_lr(self) -> bool:
+        return self.b_x != 0.0 and self.blr_ij is not None
 
     @property
     def n(self) -> int:
@@ -123,11 +142,13 @@ def exchange_wp(b_ia: np.ndarray, x: np.ndarray, no: int, nv: int) -> np.ndarray
 
 
 def apply_a(prob: OracleProblem, x: np.ndarray) -> np.ndarray:
-    """A x = de x + 2 K x - a_x W x  (Eqs. hessian, TDA; f^xc = 0)."""
+    """A x = de x + 2 K x - a_x W x [- b_x W^LR x]  (Eqs. hessian, TDA; f^xc = 0)."""
     de = prob.delta_eps()[:, None]
     y = de * x + 2.0 * coulomb(prob.b_ia, x)
     if prob.a_x != 0.0:
         y -= prob.a_x * exchange_w(prob.b_ij, prob.b_ab, x, prob.no, prob.nv)
+    if prob.has_lr:
+        y -= prob.b_x * exchange_w(prob.blr_ij, prob.blr_ab, x, prob.no, prob.nv)
     return y
 
 
@@ -135,59 +156,70 @@ def apply_apb_amb(prob: OracleProblem, x: np.ndarray):
     """((A+B) x, (A-B) x) from one evaluation of K x, W x and W' x (Eq. hessian)."""
     de = prob.delta_eps()[:, None]
     kx = coulomb(prob.b_ia, x)
+    wx = np.zeros_like(x)
+    wpx = np.zeros_like(x)
     if prob.a_x != 0.0:
-        wx = exchange_w(prob.b_ij, prob.b_ab, x, prob.no, prob.nv)
-        wpx = exchange_wp(prob.b_ia, x, prob.no, prob.nv)
-    else:
-        wx = wpx = np.zeros_like(x)
-    apb = de * x + 4.0 * kx - prob.a_x * (wx + wpx)
-    amb = de * x - prob.a_x * (wx - wpx)
+        wx += prob.a_x * exchange_w(prob.b_ij, prob.b_ab, x, prob.no, prob.nv)
+        wpx += prob.a_x * exchange_wp(prob.b_ia, x, prob.no, prob.nv)
+    if prob.has_lr:
+        wx += prob.b_x * exchange_w(prob.blr_ij, prob.blr_ab, x, prob.no, prob.nv)
+        wpx += prob.b_x * exchange_wp(prob.blr_ia, x, prob.no, prob.nv)
+    apb = de * x + 4.0 * kx - (wx + wpx)
+    amb = de * x - (wx - wpx)
     return apb, amb
 
 
-def _ris_exchange(prob: OracleProblem, x: np.ndarray, with_wp: bool):
-    """(W_ris x, W'_ris x) restricted to the active block of Sec. 3.1.
-
-    Only the leading naux_ris_k rows of the ris tensor enter (Sec. 3.2), and
-    every orbital index of the integral must be active.
-    """
+def _ris_exchange_rows(prob: OracleProblem, b_ia, b_ij, b_ab, nk: int, x: np.ndarray, with_wp: bool):
+    """(W x, W' x) from rows [0, nk) of (b_ia, b_ij, b_ab), restricted to the
+    active block of Sec. 3.1 (every orbital index of the integral active)."""
     no, nv = prob.no, prob.nv
     i0, na = prob.active_ranges()
-    nk = prob.naux_ris_k
     xc = _as_cube(x, no, nv)
     xa = xc[:, i0:, :na]
     w = np.zeros_like(xc)
     wp = np.zeros_like(xc)
     for p in range(nk):
-        bij = prob.bris_ij[p, i0:, i0:]
-        bab = prob.bris_ab[p, :na, :na]
+        bij = b_ij[p, i0:, i0:]
+        bab = b_ab[p, :na, :na]
         w[:, i0:, :na] += np.matmul(np.matmul(bij, xa), bab)
         if with_wp:
-            bia = prob.bris_ia[p, i0:, :na]
+            bia = b_ia[p, i0:, :na]
             q = np.matmul(bia, xa.transpose(0, 2, 1))
             wp[:, i0:, :na] += np.matmul(q, bia)
     return _as_cols(w), _as_cols(wp)
 
 
-def apply_t(prob: OracleProblem, x: np.ndarray) -> np.ndarray:
-    """T x for the TDA ris model: de x + 2 K_ris x - a_x W_ris^(t_cut) x."""
-    de = prob.delta_eps()[:, None]
-    y = de * x + 2.0 * coulomb(prob.bris_ia, x)
+def _ris_exchange(prob: OracleProblem, x: np.ndarray, with_wp: bool):
+    """Weighted exchange of the ris model: a_x (W_ris, W'_ris) from the leading
+    naux_ris_k rows of the ris tensor (Sec. 3.2) plus, for a range-separated
+    hybrid, b_x times the same from every row of the long-range ris tensor."""
+    w = np.zeros_like(x)
+    wp = np.zeros_like(x)
     if prob.a_x != 0.0 and prob.naux_ris_k > 0:
-        w, _ = _ris_exchange(prob, x, with_wp=False)
-        y -= prob.a_x * w
-    return y
+        a, b = _ris_exchange_rows(prob, prob.bris_ia, prob.bris_ij, prob.bris_ab, prob.naux_ris_k, x, with_wp)
+        w += prob.a_x * a
+        wp += prob.a_x * b
+    if prob.b_x != 0.0 and prob.brislr_ij is not None:
+        a, b = _ris_exchange_rows(prob, prob.brislr_ia, prob.brislr_ij, prob.brislr_ab, prob.brislr_ij.shape[0], x,
+                                  with_wp)
+        w += prob.b_x * a
+        wp += prob.b_x * b
+    return w, wp
+
+
+def apply_t(prob: OracleProblem, x: np.ndarray) -> np.ndarray:
+    """T x for the TDA ris model: de x + 2 K_ris x - a_x W_ris^(t_cut) x [- b_x W_ris^LR x]."""
+    de = prob.delta_eps()[:, None]
+    w, _ = _ris_exchange(prob, x, with_wp=False)
+    return de * x + 2.0 * coulomb(prob.bris_ia, x) - w
 
 
 def apply_tpm(prob: OracleProblem, x: np.ndarray):
     """(T_+ x, T_- x): the ris model of A+B and A-B."""
     de = prob.delta_eps()[:, None]
     kx = coulomb(prob.bris_ia, x)
-    if prob.a_x != 0.0 and prob.naux_ris_k > 0:
-        w, wp = _ris_exchange(prob, x, with_wp=True)
-    else:
-        w = wp = np.zeros_like(x)
-    return de * x + 4.0 * kx - prob.a_x * (w + wp), de * x - prob.a_x * (w - wp)
+    w, wp = _ris_exchange(prob, x, with_wp=True)
+    return de * x + 4.0 * kx - (w + wp), de * x - (w - wp)
 
 
 # ---------------------------------------------------------------------------
@@ -223,11 +255,11 @@ def dense_eri(b_full: np.ndarray) -> np.ndarray:
     return eri
 
 
-def dense_hessians(eps_occ, eps_vir, eri, a_x, occ_active=None, vir_active=None):
+def dense_hessians(eps_occ, eps_vir, eri, a_x, occ_active=None, vir_active=None, eri_lr=None, b_x=0.0):
     """Dense A and B (N x N) element by element from (pq|rs) (Eq. hessian, f^xc = 0).
 
-    A_{ia,jb} = de_ia d_ij d_ab + 2 (ia|jb) - a_x (ij|ab)
-    B_{ia,jb} =                   2 (ia|jb) - a_x (ib|ja)
+    A_{ia,jb} = de_ia d_ij d_ab + 2 (ia|jb) - a_x (ij|ab) [- b_x (ij|ab)^LR]
+    B_{ia,jb} =                   2 (ia|jb) - a_x (ib|ja) [- b_x (ib|ja)^LR]
     If active masks are given, the exchange integrals are kept only when all
     four orbitals are active (Sec. 3.1).
     """
@@ -250,6 +282,9 @@ def dense_hessians(eps_occ, eps_vir, eri, a_x, occ_active=None, vir_active=None)
                     if keep:
                         A -= a_x * eri[i, j, no + a, no + b]
                         B -= a_x * eri[i, no + b, j, no + a]
+                        if eri_lr is not None:
+                            A -= b_x * eri_lr[i, j, no + a, no + b]
+                            B -= b_x * eri_lr[i, no + b, j, no + a]
                     if ia == jb:
                         A += eps_vir[a] - eps_occ[i]
                     amat[ia, jb] = A

@@ -51,6 +51,12 @@ _STREAM_RIS_IA = 6
 _STREAM_RIS_IJ = 7
 _STREAM_RIS_AB = 8
 _STREAM_DIPOLE = 9
+_STREAM_LR_IA = 10
+_STREAM_LR_IJ = 11
+_STREAM_LR_AB = 12
+_STREAM_RISLR_IA = 13
+_STREAM_RISLR_IJ = 14
+_STREAM_RISLR_AB = 15
 
 _MASK64 = (1 << 64) - 1
 _GOLDEN = 0x9E3779B97F4A7C15
@@ -160,6 +166,17 @@ class Problem:
     bris_ij: Optional[torch.Tensor] = None
     bris_ab: Optional[torch.Tensor] = None
     seed: int = 0
+    # range-separated hybrid: exchange integrals a_x (pq|rs) + b_x (pq|rs)^LR,
+    # the long-range part factored through its own tensor C (naux_lr rows)
+    # and, in the ris model, through naux_ris_k rows of a minimal C
+    b_x: float = 0.0
+    naux_lr: int = 0
+    blr_ia: Optional[torch.Tensor] = None
+    blr_ij: Optional[torch.Tensor] = None
+    blr_ab: Optional[torch.Tensor] = None
+    brislr_ia: Optional[torch.Tensor] = None
+    brislr_ij: Optional[torch.Tensor] = None
+    brislr_ab: Optional[torch.Tensor] = None
 
     @property
     def n(self) -> int:
@@ -194,17 +211,36 @@ class Problem:
         return i0, nv_act
 
 
+def _svd_rotation(blocks, naux, rows, dev):
+    """Leading `rows` left singular directions of [blocks] (Naux x ...),
+    descending, with a deterministic sign (largest entry positive)."""
+    gram = torch.zeros((naux, naux), dtype=torch.float64, device=dev)
+    for blk in blocks:
+        m = blk.reshape(naux, -1)
+        gram += m @ m.T
+    _, vecs = torch.linalg.eigh(gram.cpu())
+    rot = torch.flip(vecs[:, naux - rows:], dims=[1]).to(dev)
+    idx = torch.argmax(rot.abs(), dim=0)
+    sgn = torch.sign(rot[idx, torch.arange(rows, device=dev)])
+    sgn[sgn == 0] = 1.0
+    return rot * sgn
+
+
 def make_problem(no: int, nv: int, naux: int, naux_ris: int = 0,
                  naux_ris_k: Optional[int] = None, a_x: float = 0.25,
                  seed: int = 0, noise: float = 0.05, device="cpu",
                  ris_source: str = "svd", t_cut: float = TCUT_HA_DEFAULT,
-                 coupling: float = 0.5) -> Problem:
+                 coupling: float = 0.5, b_x: float = 0.0, naux_lr: int = 0) -> Problem:
     """Build a synthetic problem.
 
     ris_source: "svd" (leading components of the shared SVD, then noise),
     "full" (ris tensor = the full tensor, times noise if noise > 0), or
     "none" (no ris tensor).
     coupling: target value of ||B_ia||_2^2 in Ha.
+    b_x, naux_lr: range-separated hybrid.  With naux_lr > 0 a second tensor
+    C (long-range integrals, its own streams, same distributions and scale
+    rule as B) enters the exchange with weight b_x; the ris model gets the
+    leading naux_ris_k SVD directions of C (times 1 + noise Z).
     """
     dev = torch.device(device)
     eps_occ, _ = torch.sort(-1.0 + 0.7 * counter_uniforms(seed, _STREAM_EPS_OCC, 0, no, dev))
@@ -223,6 +259,17 @@ def make_problem(no: int, nv: int, naux: int, naux_ris: int = 0,
 
     prob = Problem(no=no, nv=nv, naux=naux, eps_occ=eps_occ, eps_vir=eps_vir,
                    b_ia=b_ia, b_ij=b_ij, b_ab=b_ab, a_x=a_x, t_cut=t_cut, seed=seed)
+    if naux_lr > 0:
+        c_ia = _normal_tensor(seed, _STREAM_LR_IA, (naux_lr, no, nv), dev)
+        c2 = c_ia.reshape(naux_lr, no * nv)
+        cmax2 = float(torch.linalg.eigvalsh((c2 @ c2.T).cpu())[-1])
+        cs = math.sqrt(coupling / cmax2) if cmax2 > 0 else 0.0
+        c_ia.mul_(cs)
+        prob.b_x = float(b_x)
+        prob.naux_lr = naux_lr
+        prob.blr_ia = c_ia
+        prob.blr_ij = _normal_tensor(seed, _STREAM_LR_IJ, (naux_lr, no, no), dev, symmetric=True).mul_(cs)
+        prob.blr_ab = _normal_tensor(seed, _STREAM_LR_AB, (naux_lr, nv, nv), dev, symmetric=True).mul_(cs)
     if ris_source == "none":
         return prob
     if ris_source == "full":
@@ -265,6 +312,25 @@ def make_problem(no: int, nv: int, naux: int, naux_ris: int = 0,
     prob.naux_ris = naux_ris
     prob.naux_ris_k = int(min(naux_ris_k, naux_ris))
     prob.bris_ia, prob.bris_ij, prob.bris_ab = bris_ia, bris_ij, bris_ab
+    if naux_lr > 0:
+        rows = min(prob.naux_ris_k, naux_lr)
+        if ris_source == "full":
+            rl = None
+            rows = naux_lr
+        else:
+            rl = _svd_rotation((prob.blr_ia, prob.blr_ij, prob.blr_ab), naux_lr, rows, dev)
+
+        def rotate_lr(blk):
+            if rl is None:
+                return blk.clone()
+            return (rl.T @ blk.reshape(naux_lr, -1)).reshape((rows,) + tuple(blk.shape[1:]))
+
+        c_ia, c_ij, c_ab = rotate_lr(prob.blr_ia), rotate_lr(prob.blr_ij), rotate_lr(prob.blr_ab)
+        if noise > 0:
+            c_ia.mul_(1.0 + noise * _normal_tensor(seed, _STREAM_RISLR_IA, tuple(c_ia.shape), dev))
+            c_ij.mul_(1.0 + noise * _normal_tensor(seed, _STREAM_RISLR_IJ, tuple(c_ij.shape), dev, symmetric=True))
+            c_ab.mul_(1.0 + noise * _normal_tensor(seed, _STREAM_RISLR_AB, tuple(c_ab.shape), dev, symmetric=True))
+        prob.brislr_ia, prob.brislr_ij, prob.brislr_ab = c_ia, c_ij, c_ab
     return prob
 
 

@@ -193,3 +193,56 @@ def test_sampled_entries_match_full_products():
                                    op.b_ia, op.a_x, de[i, a], xc, i, a)
         assert abs(p - apb[i * op.nv + a, 0]) < 1e-13
         assert abs(m - amb[i * op.nv + a, 0]) < 1e-13
+
+
+def tiny_lr(no=3, nv=4, naux=5, naux_ris=4, nk=2, naux_lr=4, b_x=0.6, seed=13, t_cut=None):
+    kw = {} if t_cut is None else {"t_cut": t_cut}
+    p = make_problem(no, nv, naux, naux_ris, naux_ris_k=nk, a_x=0.16, seed=seed, b_x=b_x, naux_lr=naux_lr, **kw)
+    return OracleProblem.from_arrays(p.numpy())
+
+
+def test_range_separated_operators_match_eri_definition():
+    """A and B with a_x (pq|rs) + b_x (pq|rs)^LR, element by element."""
+    op = tiny_lr()
+    eri = ops.dense_eri(ops.full_three_index(op.b_ia, op.b_ij, op.b_ab))
+    eri_lr = ops.dense_eri(ops.full_three_index(op.blr_ia, op.blr_ij, op.blr_ab))
+    amat, bmat = ops.dense_hessians(op.eps_occ, op.eps_vir, eri, op.a_x, eri_lr=eri_lr, b_x=op.b_x)
+    x = np.random.default_rng(5).standard_normal((op.n, 3))
+    np.testing.assert_allclose(ops.apply_a(op, x), amat @ x, rtol=0, atol=1e-13)
+    p, m = ops.apply_apb_amb(op, x)
+    np.testing.assert_allclose(p, (amat + bmat) @ x, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(m, (amat - bmat) @ x, rtol=0, atol=1e-13)
+
+
+def test_range_separated_ris_model_matches_eri_definition():
+    """T with both exchange parts on the active block (Sec. 3.1)."""
+    op = tiny_lr(no=4, nv=5, naux=6, naux_ris=5, nk=2, naux_lr=4, t_cut=1.0, seed=17)
+    i0, na = op.active_ranges()
+    assert 0 < i0 < op.no and 0 < na < op.nv
+    occ = np.arange(op.no) >= i0
+    vir = np.arange(op.nv) < na
+    b = ops.full_three_index(op.bris_ia, op.bris_ij, op.bris_ab)
+    bk = ops.full_three_index(op.bris_ia[:op.naux_ris_k], op.bris_ij[:op.naux_ris_k], op.bris_ab[:op.naux_ris_k])
+    bl = ops.full_three_index(op.brislr_ia, op.brislr_ij, op.brislr_ab)
+    eri_j, eri_k, eri_l = ops.dense_eri(b), ops.dense_eri(bk), ops.dense_eri(bl)
+    a_j, b_j = ops.dense_hessians(op.eps_occ, op.eps_vir, eri_j, 0.0)
+    a_k, b_k = ops.dense_hessians(op.eps_occ, op.eps_vir, eri_k, op.a_x, occ, vir, eri_lr=eri_l, b_x=op.b_x)
+    a_0, b_0 = ops.dense_hessians(op.eps_occ, op.eps_vir, eri_k, 0.0)
+    tmat, tb = a_j + (a_k - a_0), b_j + (b_k - b_0)
+    x = np.random.default_rng(6).standard_normal((op.n, 3))
+    np.testing.assert_allclose(ops.apply_t(op, x), tmat @ x, rtol=0, atol=1e-13)
+    tp, tm = ops.apply_tpm(op, x)
+    np.testing.assert_allclose(tp, (tmat + tb) @ x, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(tm, (tmat - tb) @ x, rtol=0, atol=1e-13)
+
+
+def test_long_range_tensor_equal_to_full_tensor_adds_the_weights():
+    """With C = B the two exchange terms merge: a_x W + b_x W = (a_x + b_x) W."""
+    op = tiny_lr(naux_lr=5)
+    op.blr_ia, op.blr_ij, op.blr_ab = op.b_ia.copy(), op.b_ij.copy(), op.b_ab.copy()
+    plain = OracleProblem(no=op.no, nv=op.nv, eps_occ=op.eps_occ, eps_vir=op.eps_vir, b_ia=op.b_ia, b_ij=op.b_ij,
+                          b_ab=op.b_ab, a_x=op.a_x + op.b_x)
+    x = np.random.default_rng(7).standard_normal((op.n, 2))
+    np.testing.assert_allclose(ops.apply_a(op, x), ops.apply_a(plain, x), rtol=0, atol=1e-13)
+    for u, v in zip(ops.apply_apb_amb(op, x), ops.apply_apb_amb(plain, x)):
+        np.testing.assert_allclose(u, v, rtol=0, atol=1e-13)

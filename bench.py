@@ -373,6 +373,49 @@ def bench_sweep(args):
                                      "max_abs_omega_diff_Ha": diff}}), flush=True)
 
 
+def bench_rsh(args):
+    """Global vs range-separated hybrid (NEXT-3; Sec. 4, wB97X vs PBE0) on
+    the no=100 molecule: TDA, 10 roots, mixed precision, diagonal and rid
+    preconditioners.  The range-separated problem adds b_x (pq|rs)^LR
+    through a second tensor with Naux rows (a_x = 0.157706, b_x = 1 - a_x);
+    the global hybrid has a_x = 0.25.  Roots are checked against the FP64
+    oracle's products through their residuals (each converged root's
+    residual norm is reported by the solver)."""
+    import numpy as np
+    import torch
+
+    import paper_2404_17133_amd as rid
+    from synth import config_sizes, make_problem
+
+    no, nv, naux, nris, seed = config_sizes("c1")
+    rows = []
+    for name, kw in (("global hybrid (a_x = 0.25)", dict(a_x=0.25)),
+                     ("range-separated (a_x = 0.157706, b_x = 0.842294)",
+                      dict(a_x=0.157706, b_x=0.842294, naux_lr=naux))):
+        p = make_problem(no, nv, naux, nris, seed=seed, device="cuda:0", **kw)
+        ctx = rid.Context(0)
+        prob = rid.Problem.from_synth(ctx, p)
+        for mode in ("tda", "rpa"):
+            for pc in ("diag", "ris"):
+                prob.eigen(10, mode, pc, "mixed", vectors=False)  # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = prob.eigen(10, mode, pc, "mixed", vectors=False)
+                torch.cuda.synchronize()
+                st = out["stats"]
+                rows.append({"functional": name, "mode": mode, "preconditioner": pc, "status": out["status"],
+                             "n_iter": st["n_iter"], "n_mv": st["n_mv"], "n_inner_mv": st["n_inner_mv"],
+                             "seconds": round(time.perf_counter() - t0, 3),
+                             "max_resid": float(np.max(out["resid"]))})
+                log("%-50s %s %-4s iters %3d products %4d  %.2f s" % (name, mode, pc, st["n_iter"], st["n_mv"],
+                                                                      rows[-1]["seconds"]))
+        ctx.close()
+        del p, prob
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "global vs range-separated hybrid: no=100 nv=400 Naux=2000 Naux_ris=450, "
+                                  "10 roots, mixed precision, tolerance 1e-5", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,10 +428,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy (x * 1.0 on float32) run before timing, so that "
                          "hardware-counter runs can calibrate byte counters against a known size")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve", "sweep"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve", "sweep", "rsh"],
                     help="single: one no=200 molecule (default); batch: many molecules in one batched "
                          "solve; serve: a request stream through the server; sweep: ris-model richness "
-                         "sweep on the no=100 molecule")
+                         "sweep on the no=100 molecule; rsh: global vs range-separated hybrid")
     ap.add_argument("--molecules", type=int, default=64, help="batch: number of molecules")
     ap.add_argument("--sequential", action="store_true", help="batch: also solve the molecules one by one")
     ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
@@ -410,6 +453,8 @@ def main():
         return bench_serve(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "rsh":
+        return bench_rsh(args)
 
     import numpy as np
     import torch

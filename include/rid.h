@@ -128,6 +128,22 @@ typedef struct {
   const void* bris_ij_dev;
   const void* bris_ab_dev;
   int32_t bris_dtype;        /* RID_F64, or RID_F32: then the ris model runs in BF16 only */
+  /* Range-separated hybrid (optional; the paper's wB97X, Sec. 4): the
+   * exchange integrals are a_x (pq|rs) + b_x (pq|rs)^LR with the long-range
+   * integrals factored through a second tensor, (pq|rs)^LR = sum_Q C^Q_pq
+   * C^Q_rs, so W -> a_x W + b_x W^LR and W' likewise (Coulomb unchanged).
+   * C is borrowed like B, in b_dtype; the ris model uses every row of its own
+   * long-range tensor (bris_dtype) inside the Sec. 3.1 window.  naux_lr = 0:
+   * a global hybrid. */
+  double b_x;
+  int32_t naux_lr;
+  const void* blr_ia_dev;    /* (naux_lr, no, nv) */
+  const void* blr_ij_dev;    /* (naux_lr, no, no) symmetric slices */
+  const void* blr_ab_dev;    /* (naux_lr, nv, nv) symmetric slices */
+  int32_t naux_ris_lr;       /* rows of the ris model's long-range tensor */
+  const void* brislr_ia_dev;
+  const void* brislr_ij_dev;
+  const void* brislr_ab_dev;
 } rid_problem_desc;
 
 typedef struct {

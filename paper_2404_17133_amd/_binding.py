@@ -57,6 +57,10 @@ class rid_problem_desc(ctypes.Structure):
         ("b_dtype", ctypes.c_int32),
         ("bris_ia_dev", ctypes.c_void_p), ("bris_ij_dev", ctypes.c_void_p), ("bris_ab_dev", ctypes.c_void_p),
         ("bris_dtype", ctypes.c_int32),
+        ("b_x", ctypes.c_double), ("naux_lr", ctypes.c_int32),
+        ("blr_ia_dev", ctypes.c_void_p), ("blr_ij_dev", ctypes.c_void_p), ("blr_ab_dev", ctypes.c_void_p),
+        ("naux_ris_lr", ctypes.c_int32),
+        ("brislr_ia_dev", ctypes.c_void_p), ("brislr_ij_dev", ctypes.c_void_p), ("brislr_ab_dev", ctypes.c_void_p),
     ]
 
 

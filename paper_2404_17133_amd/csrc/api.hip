@@ -158,6 +158,13 @@ rid_status rid_problem_create(rid_context* ctx, const rid_problem_desc* d, rid_p
       RID_CHECK(d->bris_ia_dev && d->bris_ij_dev && d->bris_ab_dev, RID_ERR_INVALID_ARG, "null ris tensor pointer");
     }
     RID_CHECK(std::isfinite(d->a_x), RID_ERR_INVALID_ARG, "a_x must be finite");
+    RID_CHECK(std::isfinite(d->b_x), RID_ERR_INVALID_ARG, "b_x must be finite");
+    RID_CHECK(d->naux_lr >= 0 && d->naux_ris_lr >= 0, RID_ERR_SHAPE, "naux_lr and naux_ris_lr must be >= 0");
+    if (d->naux_lr > 0)
+      RID_CHECK(d->blr_ia_dev && d->blr_ij_dev && d->blr_ab_dev, RID_ERR_INVALID_ARG, "null long-range tensor");
+    if (d->naux_ris_lr > 0)
+      RID_CHECK(d->naux_ris > 0 && d->brislr_ia_dev && d->brislr_ij_dev && d->brislr_ab_dev, RID_ERR_INVALID_ARG,
+                "null long-range ris tensor (or no ris tensor)");
     for (int i = 0; i < d->no; ++i) RID_CHECK(std::isfinite(d->eps_occ_host[i]), RID_ERR_INVALID_ARG, "eps not finite");
     for (int a = 0; a < d->nv; ++a) RID_CHECK(std::isfinite(d->eps_vir_host[a]), RID_ERR_INVALID_ARG, "eps not finite");
     for (int i = 1; i < d->no; ++i)
@@ -198,6 +205,23 @@ rid_status rid_problem_create(rid_context* ctx, const rid_problem_desc* d, rid_p
           P->bris_ab_f = static_cast<const float*>(d->bris_ab_dev);
         }
       }
+      P->b_x = d->b_x;
+      auto lend = [](rid::LrSet& L, int rows, int dt, const void* ia, const void* ij, const void* ab) {
+        L.rows = rows;
+        L.dt = dt;
+        if (rows <= 0) return;
+        if (dt == RID_F64) {
+          L.ia = static_cast<const double*>(ia);
+          L.ij = static_cast<const double*>(ij);
+          L.ab = static_cast<const double*>(ab);
+        } else {
+          L.ia_f = static_cast<const float*>(ia);
+          L.ij_f = static_cast<const float*>(ij);
+          L.ab_f = static_cast<const float*>(ab);
+        }
+      };
+      lend(P->lr, d->naux_lr, d->b_dtype, d->blr_ia_dev, d->blr_ij_dev, d->blr_ab_dev);
+      lend(P->rislr, d->naux_ris_lr, d->bris_dtype, d->brislr_ia_dev, d->brislr_ij_dev, d->brislr_ab_dev);
       // exchange window of the ris model (energies sorted)
       const double homo = P->eps_occ.back(), lumo = P->eps_vir.front();
       if (!(d->t_cut_ha > 0.0) || !std::isfinite(d->t_cut_ha)) {

@@ -231,6 +231,9 @@ void check_operator(const rid_problem* P, int kind, int prec) {
   if (prec == PREC_F64)
     RID_CHECK((ris ? P->bris_dt : P->b_dt) == RID_F64, RID_ERR_DTYPE,
               "an FP64 product needs FP64 tensors (the problem was created with FP32 ones)");
+  if (ris && P->b_x != 0.0 && P->lr.rows > 0)
+    RID_CHECK(P->rislr.rows > 0, RID_ERR_INVALID_ARG,
+              "a range-separated problem with a ris tensor needs a long-range ris tensor");
 }
 
 namespace {
@@ -490,7 +493,17 @@ OpView<double> make_view<double>(rid_problem* P, bool ris) {
   ov.b_ij = ris ? P->bris_ij : P->b_ij;
   ov.b_ab = ris ? P->bris_ab : P->b_ab;
   ov.b_ai = ris ? P->bris_ai64.as<double>() : P->b_ai64.as<double>();
+  const LrSet& L = ris ? P->rislr : P->lr;
+  if (L.rows > 0 && P->b_x != 0.0) {
+    ov.lr_ia = L.ia;
+    ov.lr_ij = L.ij;
+    ov.lr_ab = L.ab;
+    ov.lr_ai = L.ai64.as<double>();
+    ov.naux_lr = L.rows;
+  }
   fill_window(P, ris, ov.naux_j, ov.naux_k, ov.i0, ov.no_a, ov.nv_a);
+  ov.ax = P->a_x;
+  ov.bx = P->b_x;
   ov.ris = ris;
   return ov;
 }
@@ -504,7 +517,16 @@ OpView<float> make_view<float>(rid_problem* P, bool ris) {
   ov.b_ij = P->ij32();
   ov.b_ab = P->ab32();
   ov.b_ai = P->b_ai32.as<float>();
+  if (P->lr.rows > 0 && P->b_x != 0.0) {
+    ov.lr_ia = P->lr.ia32v();
+    ov.lr_ij = P->lr.ij32v();
+    ov.lr_ab = P->lr.ab32v();
+    ov.lr_ai = P->lr.ai32.as<float>();
+    ov.naux_lr = P->lr.rows;
+  }
   fill_window(P, ris, ov.naux_j, ov.naux_k, ov.i0, ov.no_a, ov.nv_a);
+  ov.ax = P->a_x;
+  ov.bx = P->b_x;
   ov.ris = ris;
   return ov;
 }
@@ -517,7 +539,16 @@ OpView<uint16_t> make_view<uint16_t>(rid_problem* P, bool ris) {
   ov.b_ij = P->bris_ij16.as<uint16_t>();
   ov.b_ab = P->bris_ab16.as<uint16_t>();
   ov.b_ai = P->bris_ai16.as<uint16_t>();
+  if (P->rislr.rows > 0 && P->b_x != 0.0) {
+    ov.lr_ia = P->rislr.ia16.as<uint16_t>();
+    ov.lr_ij = P->rislr.ij16.as<uint16_t>();
+    ov.lr_ab = P->rislr.ab16.as<uint16_t>();
+    ov.lr_ai = P->rislr.ai16.as<uint16_t>();
+    ov.naux_lr = P->rislr.rows;
+  }
   fill_window(P, ris, ov.naux_j, ov.naux_k, ov.i0, ov.no_a, ov.nv_a);
+  ov.ax = P->a_x;
+  ov.bx = P->b_x;
   ov.ris = ris;
   return ov;
 }
@@ -529,6 +560,23 @@ struct JobPlan {
   OpView<E> ov;
   bool pair = false, exch = false;
   int no = 0, nv = 0, no_a = 0, nv_a = 0, i0 = 0, naux_j = 0, nk = 0, pc = 1, nchunks = 0, nvec = 0;
+  int nk_lr = 0, nch_sr = 0;  // long-range rows; chunks of the first (a_x) part
+
+  // Chunk c of the exchange: rows [c0, c0 + pcc) of the a_x-weighted tensor
+  // (chunks [0, nch_sr)) or of the long-range b_x-weighted one (after).
+  struct Chunk {
+    const E *ia, *ij, *ab, *ai;
+    int c0, pcc;
+    double w;
+  };
+  Chunk chunk(int c) const {
+    if (c < nch_sr) {
+      const int c0 = c * pc;
+      return Chunk{ov.b_ia, ov.b_ij, ov.b_ab, ov.b_ai, c0, std::min(pc, nk - c0), ov.ax};
+    }
+    const int c0 = (c - nch_sr) * pc;
+    return Chunk{ov.lr_ia, ov.lr_ij, ov.lr_ab, ov.lr_ai, c0, std::min(pc, nk_lr - c0), ov.bx};
+  }
   long n = 0, rows = 0, part_elems = 0, s_per_p = 0, q_per_p = 0;
   GemmChoice cw{}, cwp{};
   int ns_coul = 1;
@@ -560,7 +608,9 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       J.nv_a = J.ov.nv_a;
       J.i0 = J.ov.i0;
       J.naux_j = J.ov.naux_j;
-      J.exch = P->a_x != 0.0 && J.ov.naux_k > 0 && J.no_a > 0 && J.nv_a > 0;
+      const int nk_sr = P->a_x != 0.0 ? J.ov.naux_k : 0;
+      const int nk_lr = J.ov.bx != 0.0 ? J.ov.naux_lr : 0;
+      J.exch = nk_sr + nk_lr > 0 && J.no_a > 0 && J.nv_a > 0;
       OpWork& w = *j->work;
       w.xc.ensure(sizeof(E) * J.nvec * J.n);
       if (J.exch) {
@@ -572,13 +622,16 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       J.rows = (long)J.no_a * J.nvec;  // exchange output rows (i, v)
       J.part_elems = J.rows * J.nv_a;
       if (J.exch) {
-        J.nk = J.ov.naux_k;
+        J.nk = nk_sr;
+        J.nk_lr = nk_lr;
         J.s_per_p = (long)J.no_a * J.nvec * J.nv_a;
         J.q_per_p = (long)J.no_a * J.nvec * J.no_a;
         const long per_p = std::max(J.s_per_p, J.pair ? J.q_per_p : 0L);
         const long target = 256L << 20;  // bytes of intermediate per chunk of the auxiliary index
-        J.pc = (int)std::max<long>(1, std::min<long>(J.nk, target / std::max<long>(1, per_p * (long)sizeof(E))));
-        J.nchunks = ceil_div(J.nk, J.pc);
+        J.pc = (int)std::max<long>(1, std::min<long>(std::max(J.nk, J.nk_lr),
+                                                      target / std::max<long>(1, per_p * (long)sizeof(E))));
+        J.nch_sr = ceil_div(J.nk, J.pc);
+        J.nchunks = J.nch_sr + ceil_div(J.nk_lr, J.pc);
         int max_splits = 1;
         for (int cfg = 0; cfg < 3; ++cfg) {
           max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.nv_a, true).nsub);
@@ -657,11 +710,12 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       ProfScope ps(ctx, st, (pre + "exch_s").c_str(), 0.0, 0.0);
       for (JobPlan<E>& J : pl) {
         if (!J.exch || c >= J.nchunks) continue;
-        const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
+        const typename JobPlan<E>::Chunk ck = J.chunk(c);
+        const int c0 = ck.c0, pcc = ck.pcc;
         OpWork& w = *J.j->work;
         // one product per P, run back to back per workgroup (Xt shared)
         GemmParams g{};
-        g.A = J.ov.b_ij + (long)c0 * J.no * J.no + (long)J.i0 * J.no + J.i0;
+        g.A = ck.ij + (long)c0 * J.no * J.no + (long)J.i0 * J.no + J.i0;
         g.B = w.xt.p;
         g.C = w.s.p;
         g.M = J.no_a;
@@ -690,12 +744,13 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       ProfScope ps(ctx, st, (pre + "exch_w").c_str(), 0.0, 0.0);
       for (JobPlan<E>& J : pl) {
         if (!J.exch || c >= J.nchunks) continue;
-        const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
+        const typename JobPlan<E>::Chunk ck = J.chunk(c);
+        const int c0 = ck.c0, pcc = ck.pcc;
         const bool first = c == 0;
         OpWork& w = *J.j->work;
         GemmParams g{};
         g.A = w.s.p;
-        g.B = J.ov.b_ab + (long)c0 * J.nv * J.nv;
+        g.B = ck.ab + (long)c0 * J.nv * J.nv;
         g.C = w.wpart.p;
         g.M = (int)J.rows;
         g.N = J.nv_a;
@@ -709,7 +764,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.sAp = J.s_per_p;
         g.sBp = (long)J.nv * J.nv;
         g.sCs = J.part_elems;
-        g.alpha = 1.0;
+        g.alpha = ck.w;  // the exchange weight (a_x or b_x) is applied here
         g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
         g.order = ORDER_NM;  // a row block of S^P meets every column block of B^P_ab in L2
         ps.flops += 2.0 * J.rows * (double)J.nv_a * J.nv_a * pcc;
@@ -728,10 +783,11 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       ProfScope ps(ctx, st, (pre + "exch_q").c_str(), 0.0, 0.0);
       for (JobPlan<E>& J : pl) {
         if (!J.exch || !J.pair || c >= J.nchunks) continue;
-        const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
+        const typename JobPlan<E>::Chunk ck = J.chunk(c);
+        const int c0 = ck.c0, pcc = ck.pcc;
         OpWork& w = *J.j->work;
         GemmParams g{};
-        g.A = J.ov.b_ia + (long)c0 * J.n + (long)J.i0 * J.nv;
+        g.A = ck.ia + (long)c0 * J.n + (long)J.i0 * J.nv;
         g.B = w.xa.p;
         g.C = w.q.p;
         g.M = J.no_a;
@@ -760,12 +816,13 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       ProfScope ps(ctx, st, (pre + "exch_wp").c_str(), 0.0, 0.0);
       for (JobPlan<E>& J : pl) {
         if (!J.exch || !J.pair || c >= J.nchunks) continue;
-        const int c0 = c * J.pc, pcc = std::min(J.pc, J.nk - c0);
+        const typename JobPlan<E>::Chunk ck = J.chunk(c);
+        const int c0 = ck.c0, pcc = ck.pcc;
         const bool first = c == 0;
         OpWork& w = *J.j->work;
         GemmParams g{};
         g.A = w.q.p;
-        g.B = J.ov.b_ai + (long)c0 * J.nv * J.no + J.i0;
+        g.B = ck.ai + (long)c0 * J.nv * J.no + J.i0;
         g.C = w.wppart.p;
         g.M = (int)J.rows;
         g.N = J.nv_a;
@@ -779,7 +836,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.sAp = J.q_per_p;
         g.sBp = (long)J.nv * J.no;
         g.sCs = J.part_elems;
-        g.alpha = 1.0;
+        g.alpha = ck.w;
         g.mode = first ? GEMM_PARTIAL_SET : GEMM_PARTIAL_ADD;
         g.order = ORDER_NM;
         ps.flops += 2.0 * J.rows * (double)J.nv_a * J.no_a * pcc;
@@ -817,7 +874,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
     cb.ns_wp = ns_wp;
     cb.sstride = J.part_elems;
     cb.cj = J.pair ? 4.0 : 2.0;
-    cb.a_x = j->P->a_x;
+    cb.a_x = 1.0;  // the exchange partial sums carry their weights
     cb.pair = J.pair ? 1 : 0;
     ps.bytes += 8.0 * J.nvec * J.n * (J.pair ? 5.0 : 3.0) + asz * (ns_w + ns_wp) * J.part_elems;
     combine<Acc>(cb, J.exch ? w.wpart.as<Acc>() : nullptr, (J.exch && J.pair) ? w.wppart.as<Acc>() : nullptr, st);
@@ -957,7 +1014,8 @@ void Batcher::loop(Lane& L) {
 
 uint64_t rid_problem::footprint() const {
   return de.bytes + b_ai64.bytes + bris_ai64.bytes + b_ia32.bytes + b_ij32.bytes + b_ab32.bytes + b_ai32.bytes +
-         bris_ia16.bytes + bris_ij16.bytes + bris_ab16.bytes + bris_ai16.bytes + work.bytes();
+         bris_ia16.bytes + bris_ij16.bytes + bris_ab16.bytes + bris_ai16.bytes + work.bytes() + lr.bytes() +
+         rislr.bytes();
 }
 
 void rid_problem::ensure_f64_aux() {
@@ -973,6 +1031,13 @@ void rid_problem::ensure_f64_aux() {
     bris_ai64.ensure(sizeof(double) * (size_t)naux_ris_k * no * nv);
     rid::transpose_slices<double, double>(bris_ia, naux_ris_k, no, nv, bris_ai64.as<double>(), st);
     work = true;
+  }
+  for (rid::LrSet* L : {&lr, &rislr}) {
+    if (L->rows > 0 && L->dt == RID_F64 && !L->ai64.p) {
+      L->ai64.ensure(sizeof(double) * (size_t)L->rows * no * nv);
+      rid::transpose_slices<double, double>(L->ia, L->rows, no, nv, L->ai64.as<double>(), st);
+      work = true;
+    }
   }
   // the copies are read from other streams too
   if (work) RID_HIP(hipStreamSynchronize(st));
@@ -995,6 +1060,22 @@ void rid_problem::ensure_f32() {
   } else {
     b_ai32.ensure(sizeof(float) * naux * n);
     rid::transpose_slices<float, float>(b_ia_f, naux, no, nv, b_ai32.as<float>(), st);
+  }
+  if (lr.rows > 0) {
+    const long r = lr.rows;
+    if (lr.dt == RID_F64) {
+      lr.ia32.ensure(sizeof(float) * r * n);
+      rid::cast_copy<double, float>(lr.ia, r * n, lr.ia32.as<float>(), st);
+      lr.ij32.ensure(sizeof(float) * (size_t)r * no * no);
+      rid::cast_copy<double, float>(lr.ij, r * no * no, lr.ij32.as<float>(), st);
+      lr.ab32.ensure(sizeof(float) * (size_t)r * nv * nv);
+      rid::cast_copy<double, float>(lr.ab, r * nv * nv, lr.ab32.as<float>(), st);
+      lr.ai32.ensure(sizeof(float) * r * n);
+      rid::transpose_slices<double, float>(lr.ia, lr.rows, no, nv, lr.ai32.as<float>(), st);
+    } else {
+      lr.ai32.ensure(sizeof(float) * r * n);
+      rid::transpose_slices<float, float>(lr.ia_f, lr.rows, no, nv, lr.ai32.as<float>(), st);
+    }
   }
   RID_HIP(hipStreamSynchronize(st));
 }
@@ -1022,6 +1103,25 @@ void rid_problem::ensure_bf16() {
       rid::cast_copy<float, uint16_t>(bris_ij_f, (long)naux_ris_k * no * no, bris_ij16.as<uint16_t>(), st);
       rid::cast_copy<float, uint16_t>(bris_ab_f, (long)naux_ris_k * nv * nv, bris_ab16.as<uint16_t>(), st);
       rid::transpose_slices<float, uint16_t>(bris_ia_f, naux_ris_k, no, nv, bris_ai16.as<uint16_t>(), st);
+    }
+  }
+  if (rislr.rows > 0) {
+    rid::LrSet& L = rislr;
+    const long r = L.rows;
+    L.ia16.ensure(2 * (size_t)r * n);
+    L.ij16.ensure(2 * (size_t)r * no * no);
+    L.ab16.ensure(2 * (size_t)r * nv * nv);
+    L.ai16.ensure(2 * (size_t)r * n);
+    if (L.dt == RID_F64) {
+      rid::cast_copy<double, uint16_t>(L.ia, r * n, L.ia16.as<uint16_t>(), st);
+      rid::cast_copy<double, uint16_t>(L.ij, r * no * no, L.ij16.as<uint16_t>(), st);
+      rid::cast_copy<double, uint16_t>(L.ab, r * nv * nv, L.ab16.as<uint16_t>(), st);
+      rid::transpose_slices<double, uint16_t>(L.ia, L.rows, no, nv, L.ai16.as<uint16_t>(), st);
+    } else {
+      rid::cast_copy<float, uint16_t>(L.ia_f, r * n, L.ia16.as<uint16_t>(), st);
+      rid::cast_copy<float, uint16_t>(L.ij_f, r * no * no, L.ij16.as<uint16_t>(), st);
+      rid::cast_copy<float, uint16_t>(L.ab_f, r * nv * nv, L.ab16.as<uint16_t>(), st);
+      rid::transpose_slices<float, uint16_t>(L.ia_f, L.rows, no, nv, L.ai16.as<uint16_t>(), st);
     }
   }
   RID_HIP(hipStreamSynchronize(st));

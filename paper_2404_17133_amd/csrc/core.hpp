@@ -164,8 +164,31 @@ struct OpView {
   const E* b_ai = nullptr;  // (>= naux_k, nv, no): b_ia transposed per slice
   int naux_j = 0;           // rows in the Coulomb part
   int naux_k = 0;           // leading rows in the exchange part
+  // long-range exchange tensor of a range-separated hybrid (naux_lr rows)
+  const E *lr_ia = nullptr, *lr_ij = nullptr, *lr_ab = nullptr, *lr_ai = nullptr;
+  int naux_lr = 0;
+  double ax = 0.0, bx = 0.0;        // weights of the two exchange parts
   int i0 = 0, no_a = 0, nv_a = 0;  // exchange window
   bool ris = false;                 // profiling family prefix
+};
+
+// Long-range exchange tensor C of a range-separated hybrid, borrowed in FP64
+// or FP32, with the copies the products read (transposes, casts).
+struct LrSet {
+  int rows = 0;
+  int dt = RID_F64;
+  const double *ia = nullptr, *ij = nullptr, *ab = nullptr;
+  const float *ia_f = nullptr, *ij_f = nullptr, *ab_f = nullptr;
+  DevBuf ai64, ia32, ij32, ab32, ai32, ia16, ij16, ab16, ai16;
+  explicit LrSet(rid_context* c)
+      : ai64(c), ia32(c), ij32(c), ab32(c), ai32(c), ia16(c), ij16(c), ab16(c), ai16(c) {}
+  size_t bytes() const {
+    return ai64.bytes + ia32.bytes + ij32.bytes + ab32.bytes + ai32.bytes + ia16.bytes + ij16.bytes + ab16.bytes +
+           ai16.bytes;
+  }
+  const float* ia32v() const { return dt == RID_F32 ? ia_f : ia32.as<float>(); }
+  const float* ij32v() const { return dt == RID_F32 ? ij_f : ij32.as<float>(); }
+  const float* ab32v() const { return dt == RID_F32 ? ab_f : ab32.as<float>(); }
 };
 
 }  // namespace rid
@@ -191,9 +214,12 @@ struct rid_problem {
   rid::DevBuf b_ia32, b_ij32, b_ab32, b_ai32;
   rid::DevBuf bris_ia16, bris_ij16, bris_ab16, bris_ai16;
   rid::OpWork work;
+  // range-separated hybrid: exchange a_x (pq|rs) + b_x (pq|rs)^LR
+  double b_x = 0.0;
+  rid::LrSet lr, rislr;
   explicit rid_problem(rid_context* c)
       : ctx(c), de(c), b_ai64(c), bris_ai64(c), b_ia32(c), b_ij32(c), b_ab32(c), b_ai32(c), bris_ia16(c),
-        bris_ij16(c), bris_ab16(c), bris_ai16(c), work(c) {}
+        bris_ij16(c), bris_ab16(c), bris_ai16(c), work(c), lr(c), rislr(c) {}
   long n() const { return (long)no * nv; }
   uint64_t footprint() const;
   // lazily built copies

@@ -152,7 +152,10 @@ class Problem:
     """
 
     def __init__(self, ctx: Context, eps_occ, eps_vir, b_ia, b_ij, b_ab, a_x: float,
-                 bris_ia=None, bris_ij=None, bris_ab=None, naux_ris_k: int = 0, t_cut: float = 0.0):
+                 bris_ia=None, bris_ij=None, bris_ab=None, naux_ris_k: int = 0, t_cut: float = 0.0,
+                 b_x: float = 0.0, blr=None, brislr=None):
+        """blr / brislr: optional (ia, ij, ab) long-range tensors of a
+        range-separated hybrid (weight b_x), full and ris model."""
         self.ctx = ctx
         self.eps_occ = np.ascontiguousarray(np.asarray(eps_occ, dtype=np.float64))
         self.eps_vir = np.ascontiguousarray(np.asarray(eps_vir, dtype=np.float64))
@@ -168,9 +171,18 @@ class Problem:
             _need_dev(bris_ia, (nris, no, nv), "bris_ia", fp)
             _need_dev(bris_ij, (nris, no, no), "bris_ij", (bris_ia.dtype,))
             _need_dev(bris_ab, (nris, nv, nv), "bris_ab", (bris_ia.dtype,))
+        nlr = nrislr = 0
+        if blr is not None:
+            nlr = blr[0].shape[0]
+            for t, shp, nm in zip(blr, ((nlr, no, nv), (nlr, no, no), (nlr, nv, nv)), ("ia", "ij", "ab")):
+                _need_dev(t, shp, "blr_" + nm, (b_ia.dtype,))
+        if brislr is not None:
+            nrislr = brislr[0].shape[0]
+            for t, shp, nm in zip(brislr, ((nrislr, no, nv), (nrislr, no, no), (nrislr, nv, nv)), ("ia", "ij", "ab")):
+                _need_dev(t, shp, "brislr_" + nm, (bris_ia.dtype,))
         self.no, self.nv, self.naux, self.naux_ris = no, nv, naux, nris
         self.n = no * nv
-        self._keep = (b_ia, b_ij, b_ab, bris_ia, bris_ij, bris_ab)
+        self._keep = (b_ia, b_ij, b_ab, bris_ia, bris_ij, bris_ab, blr, brislr)
         d = B.rid_problem_desc()
         d.no, d.nv, d.naux, d.naux_ris, d.naux_ris_k = no, nv, naux, nris, naux_ris_k
         d.a_x = a_x
@@ -183,6 +195,13 @@ class Problem:
         if nris:
             d.bris_ia_dev, d.bris_ij_dev, d.bris_ab_dev = bris_ia.data_ptr(), bris_ij.data_ptr(), bris_ab.data_ptr()
             d.bris_dtype = B.RID_F64 if bris_ia.dtype == torch.float64 else B.RID_F32
+        d.b_x = b_x
+        d.naux_lr = nlr
+        if nlr:
+            d.blr_ia_dev, d.blr_ij_dev, d.blr_ab_dev = (t.data_ptr() for t in blr)
+        d.naux_ris_lr = nrislr
+        if nrislr:
+            d.brislr_ia_dev, d.brislr_ij_dev, d.brislr_ab_dev = (t.data_ptr() for t in brislr)
         h = ctypes.c_void_p()
         ctx.check(B.lib.rid_problem_create(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
         self.handle = h
@@ -191,8 +210,10 @@ class Problem:
     @classmethod
     def from_synth(cls, ctx: Context, p) -> "Problem":
         """From a synth.Problem whose tensors live on the context's device."""
+        lr = (p.blr_ia, p.blr_ij, p.blr_ab) if getattr(p, "naux_lr", 0) else None
+        rislr = (p.brislr_ia, p.brislr_ij, p.brislr_ab) if getattr(p, "brislr_ia", None) is not None else None
         return cls(ctx, p.eps_occ.cpu().numpy(), p.eps_vir.cpu().numpy(), p.b_ia, p.b_ij, p.b_ab, p.a_x,
-                   p.bris_ia, p.bris_ij, p.bris_ab, p.naux_ris_k, p.t_cut)
+                   p.bris_ia, p.bris_ij, p.bris_ab, p.naux_ris_k, p.t_cut, getattr(p, "b_x", 0.0), lr, rislr)
 
     def window(self):
         i0, na = ctypes.c_int32(), ctypes.c_int32()

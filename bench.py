@@ -209,39 +209,58 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def f64_problem(rid, ctx, d, dipoles=False):
+    """A synthetic molecule lent to the library as FP64 tensors: FP64 solves
+    use them directly, mixed-precision solves through the FP32/BF16 copies the
+    library makes.  Returns (problem, dipole block or None)."""
+    from synth import make_dipoles, make_problem
+
+    p = make_problem(d["no"], d["nv"], d["naux"], d["naux_ris"], naux_ris_k=d["naux_ris_k"], seed=d["seed"],
+                     device="cuda:0")
+    dip = make_dipoles(p, 3) if dipoles else None
+    return rid.Problem.from_synth(ctx, p), dip
+
+
 def bench_serve(args):
     """Served stream: requests of synth.serve_trace (no log-uniform in
     [20, no_max], 70% TDA/RPA eigen k 5..20, 30% polarizability 3 RHS x 3
     frequencies), mixed precision, rid preconditioner.  First all requests
     arrive at once (saturated throughput), then the same requests arrive as a
-    Poisson stream at `load` times that throughput (latency percentiles)."""
+    Poisson stream at each of `loads` times that throughput (latency
+    percentiles).  With --fp64 the molecules are kept in FP64 and the same
+    requests are also served by the FP64 path: saturated, and replaying the
+    arrival times of the mixed run at the first load."""
     import numpy as np
     import torch
 
     import paper_2404_17133_amd as rid
     from synth import serve_trace
 
+    loads = [float(x) for x in args.loads.split(",")] if args.loads else [args.load]
     trace = serve_trace(args.requests, no_max=args.no_max)
     ctx = rid.Context(0)
     t0 = time.time()
     probs, dips = [None] * len(trace), [None] * len(trace)
+    make = f64_problem if args.fp64 else f32_problem
     for r in sorted(range(len(trace)), key=lambda i: -trace[i]["no"]):
-        probs[r], dips[r] = f32_problem(rid, ctx, trace[r], dipoles=trace[r]["kind"] != "eigen")
+        probs[r], dips[r] = make(rid, ctx, trace[r], dipoles=trace[r]["kind"] != "eigen")
     torch.cuda.synchronize()
     log("%d requests' molecules generated in %.1f s" % (len(trace), time.time() - t0))
-    opts = rid.default_opts("ris", "mixed")
-    reqs, keeps, roots = [], [], 0
-    for d, dp in zip(trace, dips):
-        if d["kind"] == "eigen":
-            r, kp = rid.make_request("eigen", opts, k=d["k"], mode=d["mode"])
-            roots += d["k"]
-        else:
-            r, kp = rid.make_request("polarizability", opts, p=dp, omegas=d["omegas"])
-            roots += 3 * len(d["omegas"])
-        reqs.append(r)
-        keeps.append(kp)
 
-    def serve(gaps):
+    def requests(opts):
+        reqs, keeps, roots = [], [], 0
+        for d, dp in zip(trace, dips):
+            if d["kind"] == "eigen":
+                r, kp = rid.make_request("eigen", opts, k=d["k"], mode=d["mode"])
+                roots += d["k"]
+            else:
+                r, kp = rid.make_request("polarizability", opts, p=dp, omegas=d["omegas"])
+                roots += 3 * len(d["omegas"])
+            reqs.append(r)
+            keeps.append(kp)
+        return reqs, keeps, roots
+
+    def serve(reqs, keeps, gaps):
         srv = rid.Server(ctx, hbm_budget_bytes=args.hbm_budget_gb << 30, max_slots=args.slots)
         tick = []
         ts = time.perf_counter()
@@ -259,14 +278,24 @@ def bench_serve(args):
             raise RuntimeError("served requests failed: %s" % bad)
         lat = np.array([(x["t_done_ms"] - x["t_arrival_ms"]) * 1e-3 for x in res])
         span = (max(x["t_done_ms"] for x in res) - min(x["t_arrival_ms"] for x in res)) * 1e-3
-        return lat, span
+        return lat, span, res
 
-    lat_s, span_s = serve([0.0] * len(trace))
+    def pct(lat):
+        return {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)}
+
+    reqs, keeps, roots = requests(rid.default_opts("ris", "mixed"))
+    lat_s, span_s, res_mixed = serve(reqs, keeps, [0.0] * len(trace))
     rate = len(trace) / span_s
     log("saturated: %.2f s for %d requests (%.3f req/s)" % (span_s, len(trace), rate))
-    gaps = [d["gap"] / (args.load * rate) for d in trace]
-    lat_p, span_p = serve(gaps)
-    log("Poisson at %.2f x saturation: %.2f s" % (args.load, span_p))
+    runs = []
+    for load in loads:
+        gaps = [d["gap"] / (load * rate) for d in trace]
+        lat_p, span_p, _ = serve(reqs, keeps, gaps)
+        log("Poisson at %.2f x saturation: %.2f s, p50 %.2f s, p99 %.2f s"
+            % (load, span_p, np.percentile(lat_p, 50), np.percentile(lat_p, 99)))
+        runs.append({"load": load, "rate_req_per_s": round(load * rate, 4), "roots_per_s": round(roots / span_p, 4),
+                     "latency_s": pct(lat_p), "gaps": gaps})
+    first = runs[0]
     out = {
         "metric": "converged roots/sec + p50/p99 solve latency, mixed-precision vs FP64 Davidson",
         "value": round(roots / span_s, 4), "unit": "roots/s", "n_gpus": 1, "steps": 1, "warmup": 0,
@@ -276,14 +305,31 @@ def bench_serve(args):
                                "k 5..20, 30%% polarizability 3 RHS x 3 frequencies, rid preconditioner, mixed "
                                "precision, %d slots" % (len(trace), args.no_max, args.slots),
                    "roots_per_pass": roots},
-        "latency_s": {"p50": round(float(np.percentile(lat_p, 50)), 3),
-                      "p99": round(float(np.percentile(lat_p, 99)), 3),
-                      "arrivals": "Poisson at %.2f x the saturated request rate (%.4f req/s)"
-                                  % (args.load, args.load * rate)},
-        "poisson_roots_per_s": round(roots / span_p, 4),
-        "saturated_latency_s": {"p50": round(float(np.percentile(lat_s, 50)), 3),
-                                "p99": round(float(np.percentile(lat_s, 99)), 3)},
+        "latency_s": dict(first["latency_s"], arrivals="Poisson at %.2f x the saturated request rate (%.4f req/s)"
+                          % (first["load"], first["rate_req_per_s"])),
+        "poisson_roots_per_s": first["roots_per_s"],
+        "loads": [{k: v for k, v in r.items() if k != "gaps"} for r in runs],
+        "saturated_latency_s": pct(lat_s),
     }
+    if args.fp64:
+        reqs64, keeps64, _ = requests(rid.default_opts("ris", "fp64"))
+        lat64, span64, res64 = serve(reqs64, keeps64, [0.0] * len(trace))
+        log("FP64 saturated: %.2f s" % span64)
+        lat64p, span64p, _ = serve(reqs64, keeps64, first["gaps"])
+        log("FP64 replay of the mixed arrivals at %.2f x: %.2f s" % (first["load"], span64p))
+        dom, dal = 0.0, 0.0
+        for a, b in zip(res_mixed, res64):
+            if "omega" in a:
+                dom = max(dom, float(np.max(np.abs(a["omega"] - b["omega"]))))
+            if "alpha" in a:
+                dal = max(dal, float(np.max(np.abs(a["alpha"] - b["alpha"]) / np.abs(b["alpha"]).max())))
+        out["fp64_gpu"] = {
+            "value": round(roots / span64, 4), "unit": "roots/s", "saturated_latency_s": pct(lat64),
+            "replay": {"arrivals": "the mixed run's arrival times at %.2f x" % first["load"],
+                       "roots_per_s": round(roots / span64p, 4), "latency_s": pct(lat64p)},
+            "speedup_mixed_vs_fp64": round(span64 / span_s, 3),
+            "max_abs_omega_diff_Ha": dom, "max_rel_alpha_diff": dal,
+        }
     ctx.close()
     print(json.dumps(out), flush=True)
 
@@ -437,6 +483,8 @@ def main():
     ap.add_argument("--requests", type=int, default=24, help="serve: number of requests")
     ap.add_argument("--no-max", type=int, default=300, help="serve: largest number of occupied orbitals")
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturated rate")
+    ap.add_argument("--loads", default=None, help="serve: comma-separated list of loads (overrides --load)")
+    ap.add_argument("--fp64", action="store_true", help="serve: also serve the same requests in FP64")
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent requests")
     ap.add_argument("--hbm-budget-gb", type=int, default=96, help="serve: admission budget")
     args = ap.parse_args()

@@ -636,6 +636,101 @@ __global__ __launch_bounds__(LB) void lu_cm_kernel(double* mats, double* rhs, in
   }
 }
 
+// The same elimination for systems small enough to live in LDS (m <= 128:
+// 132 KB with an odd leading dimension): the matrix and the right-hand side
+// are copied in once, every column step works on LDS only, with the trailing
+// update spread over all threads of the block (not one row per thread), and
+// only the solution is written back.  Pivot choice, guard and operation
+// order per element are those of lu_cm_kernel.
+constexpr int LU_LDS_MAX = 128;
+
+__global__ __launch_bounds__(LB) void lu_lds_kernel(const double* mats, double* rhs, int m) {
+  __shared__ double sa[LU_LDS_MAX * (LU_LDS_MAX + 1)];
+  __shared__ double sg[LU_LDS_MAX];
+  __shared__ double rv[LB / 64];
+  __shared__ int ri[LB / 64];
+  const int ld = m | 1;  // odd: the row swap's strided accesses spread over the banks
+  const double* a = mats + (long)blockIdx.x * m * m;
+  double* g = rhs + (long)blockIdx.x * m;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < m * m; e += LB) {
+    const int k = e / m, i = e - k * m;
+    sa[k * ld + i] = a[e];
+  }
+  for (int i = tid; i < m; i += LB) sg[i] = g[i];
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    double best = -1.0;
+    int bi = m;
+    for (int i = j + tid; i < m; i += LB) {
+      const double v = fabs(sa[j * ld + i]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      rv[wave] = best;
+      ri[wave] = bi;
+    }
+    __syncthreads();
+    double pb = -1.0;
+    int p = j;
+    for (int w = 0; w < LB / 64; ++w)
+      if (rv[w] > pb || (rv[w] == pb && ri[w] < p)) {
+        pb = rv[w];
+        p = ri[w];
+      }
+    if (p >= m) p = j;
+    if (p != j) {
+      for (int k = tid; k < m; k += LB) {
+        const double t = sa[k * ld + j];
+        sa[k * ld + j] = sa[k * ld + p];
+        sa[k * ld + p] = t;
+      }
+      if (tid == 0) {
+        const double t = sg[j];
+        sg[j] = sg[p];
+        sg[p] = t;
+      }
+    }
+    __syncthreads();
+    // multipliers of column j and the right-hand side
+    const double pv = guard_pivot(sa[j * ld + j]);
+    const double gj = sg[j];
+    for (int i = j + 1 + tid; i < m; i += LB) {
+      const double l = sa[j * ld + i] / pv;
+      sa[j * ld + i] = l;
+      sg[i] -= l * gj;
+    }
+    __syncthreads();
+    // trailing update, element (i, k) of the (m-j-1)^2 block per thread
+    const int r = m - j - 1;
+    for (int e = tid; e < r * r; e += LB) {
+      const int kk = e / r, ii = e - kk * r;
+      const int i = j + 1 + ii, k = j + 1 + kk;
+      sa[k * ld + i] -= sa[j * ld + i] * sa[k * ld + j];
+    }
+    __syncthreads();
+  }
+  for (int j = m - 1; j >= 0; --j) {
+    const double yj = sg[j] / guard_pivot(sa[j * ld + j]);
+    __syncthreads();
+    if (tid == 0) sg[j] = yj;
+    for (int i = tid; i < j; i += LB) sg[i] -= sa[j * ld + i] * yj;
+    __syncthreads();
+  }
+  for (int i = tid; i < m; i += LB) g[i] = sg[i];
+}
+
 // Pair systems of the inner full-TDDFT solve.  System q of right-hand side
 // b = sys_b[q]: type 0 (shift s != 0): (t- t+ - s^2 I) y = t- g1 + s g2;
 // type 1 (s = 0): t+ y = g1; type 2 (s = 0): t- y' = g2.  Matrices are
@@ -838,7 +933,10 @@ void small_lu_solve(double* mats, double* rhs, int m, int nb, hipStream_t s) {
 
 void small_lu_solve_cm(double* mats, double* rhs, int m, int nb, hipStream_t s) {
   if (m <= 0 || nb <= 0) return;
-  hipLaunchKernelGGL(lu_cm_kernel, dim3(nb), dim3(LB), 0, s, mats, rhs, m);
+  if (m <= LU_LDS_MAX)
+    hipLaunchKernelGGL(lu_lds_kernel, dim3(nb), dim3(LB), 0, s, mats, rhs, m);
+  else
+    hipLaunchKernelGGL(lu_cm_kernel, dim3(nb), dim3(LB), 0, s, mats, rhs, m);
   RID_HIP(hipGetLastError());
 }
 

@@ -11,7 +11,10 @@
 // Readings of the paper taken here (shared with the CPU reference the tests
 // compare against):
 //  * Gram-Schmidt: unit-normalise, project out the basis twice, then the
-//    already accepted new directions twice, drop below 1e-8;
+//    already accepted new directions twice, drop below 1e-8 (a block whose
+//    directions stay well apart after the first step is orthonormalised
+//    within itself by two Cholesky-QR passes instead, which spans the same
+//    space and drops nothing);
 //  * diagonal preconditioner: de = eps_a - eps_i, denominators guarded at
 //    +-1e-8;
 //  * inner solve: block Galerkin over a shared subspace, unit-normalised
@@ -146,9 +149,62 @@ struct Basis {
 
 // Orthonormalise nnew directions W (row-major, ld N; overwritten) against the
 // basis and each other, append the accepted ones.  Returns the number added.
-// Every step runs on the device; direction j is written to basis slot m0 + j
-// (zero when dropped), so that the host reads the norms once, at the end, and
-// then closes the gaps left by dropped directions.
+// Every step runs on the device.  After the projection against the basis,
+// the block is orthonormalised within itself by one of two routes:
+//  * Cholesky QR, twice: G = W^T W = L L^T, W <- W L^{-T}, repeated on the
+//    result.  Taken when every Cholesky pivot of the first pass is at least
+//    kCholQrMinPivot (each direction keeps at least that fraction of its
+//    length against the ones before it): then the first pass is accurate
+//    to about (n / kCholQrMinPivot)^2 * eps and the second restores full
+//    orthonormality.  No direction is dropped.  A handful of launches for
+//    the whole block.
+//  * otherwise modified Gram-Schmidt, twice per direction, with the drop
+//    test: direction j is written to basis slot m0 + j (zero when dropped),
+//    the host reads the norms once, at the end, and then closes the gaps
+//    left by dropped directions.
+// Both give the Q of the QR factorisation of the projected block (the same
+// in exact arithmetic); only the second can drop.
+constexpr double kCholQrMinPivot = 1e-3;
+
+bool block_cholqr2(Eng& E, Basis& B, double* W, int n, const double* nrm_d) {
+  const long N = E.N;
+  const int m0 = B.m;
+  E.tmp2.ensure(sizeof(double) * (size_t)(2 * n * n + 8));
+  E.ints.ensure(sizeof(int) * 2);
+  double* G = E.tmp2.as<double>();
+  double* Li = G + (size_t)n * n;
+  int* info = E.ints.as<int>();
+  {
+    RedScratch rs = E.rs(n, n);
+    gram(W, N, n, W, N, n, N, G, n, rs, E.st);
+  }
+  small_chol(G, n, n, info, E.st);
+  std::vector<double> hl((size_t)n * n), hn(n);
+  int hinfo = 1;
+  RID_HIP(hipMemcpyAsync(hl.data(), G, sizeof(double) * n * n, hipMemcpyDeviceToHost, E.st));
+  RID_HIP(hipMemcpyAsync(hn.data(), nrm_d, sizeof(double) * n, hipMemcpyDeviceToHost, E.st));
+  RID_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, E.st));
+  E.sync();
+  if (hinfo != 0) return false;
+  for (int j = 0; j < n; ++j) {
+    const double d = hl[(size_t)j * n + j];
+    if (!std::isfinite(hn[j]) || hn[j] == 0.0 || !std::isfinite(d) || !(d >= kCholQrMinPivot)) return false;
+  }
+  // first pass into the basis slots, second pass back into W, then copy
+  small_trinv_lower(G, n, n, Li, n, E.st);
+  combo(W, N, n, Li, 1, n, n, N, 1.0, 0.0, B.V(m0), N, E.st);  // T_j = sum_i L^{-1}[j][i] W_i
+  {
+    RedScratch rs = E.rs(n, n);
+    gram(B.V(m0), N, n, B.V(m0), N, n, N, G, n, rs, E.st);
+  }
+  small_chol(G, n, n, info, E.st);
+  small_trinv_lower(G, n, n, Li, n, E.st);
+  combo(B.V(m0), N, n, Li, 1, n, n, N, 1.0, 0.0, W, N, E.st);
+  RID_HIP(hipMemcpyAsync(B.V(m0), W, sizeof(double) * (size_t)n * N, hipMemcpyDeviceToDevice, E.st));
+  B.m = m0 + n;
+  return true;
+}
+
 int append_orthonormal(Eng& E, Basis& B, double* W, int nnew, double drop_tol = 1e-8) {
   if (nnew <= 0) return 0;
   ProfScope ps(E.P->ctx, E.st, "orthonormalize", 0.0, 0.0);
@@ -172,6 +228,7 @@ int append_orthonormal(Eng& E, Basis& B, double* W, int nnew, double drop_tol = 
     }
   }
   const int m0 = B.m;
+  if (nnew >= 2 && block_cholqr2(E, B, W, nnew, nrm_d)) return nnew;
   E.tmp2.ensure(sizeof(double) * (size_t)(nnew + 8));
   double* c = E.tmp2.as<double>();
   for (int j = 0; j < nnew; ++j) {

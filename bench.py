@@ -99,9 +99,10 @@ def measured_traffic(family: str, dtype: str):
         return None
     t = {"f32": "float", "bf16": "bf16_t", "f64": "double"}[dtype]
     fam = family[4:] if family.startswith("ris_") else family
-    # dispatch-weighted mean over the tile shapes the autotuner picked
+    # dispatch-weighted mean over the tile shapes the autotuner picked (the
+    # counter table only: the summary's second table lists rates)
     n_tot, b_tot = 0, 0.0
-    for line in text.splitlines():
+    for line in text.split("Achieved rate")[0].splitlines():
         cells = [c.strip() for c in line.split("|")]
         if len(cells) > 5 and cells[1].startswith("gemm_nt<%s," % t) and cells[1].endswith("[%s]" % fam):
             n = int(cells[2])

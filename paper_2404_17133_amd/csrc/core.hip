@@ -561,6 +561,11 @@ struct JobPlan {
   bool pair = false, exch = false;
   int no = 0, nv = 0, no_a = 0, nv_a = 0, i0 = 0, naux_j = 0, nk = 0, pc = 1, nchunks = 0, nvec = 0;
   int nk_lr = 0, nch_sr = 0;  // long-range rows; chunks of the first (a_x) part
+  // K extent of the contractions over the active virtuals: nv_a rounded up
+  // to a whole 16-byte chunk when that stays inside a row of B (the extra
+  // columns meet zeros in the padded vector layouts), so that they can use
+  // 16-byte loads; nv_a otherwise.
+  int kv = 0;
 
   // Chunk c of the exchange: rows [c0, c0 + pcc) of the a_x-weighted tensor
   // (chunks [0, nch_sr)) or of the long-range b_x-weighted one (after).
@@ -611,20 +616,25 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       const int nk_sr = P->a_x != 0.0 ? J.ov.naux_k : 0;
       const int nk_lr = J.ov.bx != 0.0 ? J.ov.naux_lr : 0;
       J.exch = nk_sr + nk_lr > 0 && J.no_a > 0 && J.nv_a > 0;
+      {
+        const int vw = 16 / (int)sizeof(E);
+        const int up = ceil_div(J.nv_a, vw) * vw;
+        J.kv = up <= J.nv ? up : J.nv_a;
+      }
       OpWork& w = *j->work;
       w.xc.ensure(sizeof(E) * J.nvec * J.n);
       if (J.exch) {
-        w.xa.ensure(sizeof(E) * (size_t)J.nvec * J.no_a * J.nv_a);
-        w.xt.ensure(sizeof(E) * (size_t)J.nvec * J.no_a * J.nv_a);
+        w.xa.ensure(sizeof(E) * (size_t)J.nvec * J.no_a * J.kv);
+        w.xt.ensure(sizeof(E) * (size_t)J.nvec * J.no_a * J.kv);
       }
-      prep_x<E>(j->x, J.nvec, J.no, J.nv, J.i0, J.no_a, J.nv_a, w.xc.as<E>(), J.exch ? w.xa.as<E>() : nullptr,
+      prep_x<E>(j->x, J.nvec, J.no, J.nv, J.i0, J.no_a, J.nv_a, J.kv, w.xc.as<E>(), J.exch ? w.xa.as<E>() : nullptr,
                 J.exch ? w.xt.as<E>() : nullptr, st);
       J.rows = (long)J.no_a * J.nvec;  // exchange output rows (i, v)
       J.part_elems = J.rows * J.nv_a;
       if (J.exch) {
         J.nk = nk_sr;
         J.nk_lr = nk_lr;
-        J.s_per_p = (long)J.no_a * J.nvec * J.nv_a;
+        J.s_per_p = (long)J.no_a * J.nvec * J.kv;
         J.q_per_p = (long)J.no_a * J.nvec * J.no_a;
         const long per_p = std::max(J.s_per_p, J.pair ? J.q_per_p : 0L);
         const long target = 256L << 20;  // bytes of intermediate per chunk of the auxiliary index
@@ -634,7 +644,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         J.nchunks = J.nch_sr + ceil_div(J.nk_lr, J.pc);
         int max_splits = 1;
         for (int cfg = 0; cfg < 3; ++cfg) {
-          max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.nv_a, true).nsub);
+          max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.kv, true).nsub);
           max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.no_a, true).nsub);
         }
         w.s.ensure(sizeof(E) * (size_t)J.pc * J.s_per_p);
@@ -719,14 +729,14 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.B = w.xt.p;
         g.C = w.s.p;
         g.M = J.no_a;
-        g.N = J.nvec * J.nv_a;
+        g.N = J.nvec * J.kv;
         g.K = J.no_a;
         g.np = pcc;
         g.pps = 1;
         g.nz2 = 1;
         g.lda = J.no;
         g.ldb = J.no_a;
-        g.ldc = (long)J.nvec * J.nv_a;
+        g.ldc = (long)J.nvec * J.kv;
         g.sAp = (long)J.no * J.no;
         g.sBp = 0;
         g.sCs = J.s_per_p;
@@ -735,7 +745,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.order = ORDER_ZIN;  // each XCD keeps its share of Xt in L2 across all P
         ps.flops += 2.0 * J.no_a * (double)J.nvec * J.nv_a * J.no_a * pcc;
         ps.bytes += esz * ((double)pcc * J.no_a * J.no_a + (double)J.nvec * J.nv_a * J.no_a + (double)pcc * J.s_per_p);
-        plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.nv_a, 1, pcc, J.no_a, true, st);
+        plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.kv, 1, pcc, J.no_a, true, st);
       }
       stage.launch(ctx, GF_EXCH_S, st);
     }
@@ -754,11 +764,11 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.C = w.wpart.p;
         g.M = (int)J.rows;
         g.N = J.nv_a;
-        g.K = J.nv_a;
+        g.K = J.kv;
         g.np = pcc;
         g.pps = 1;
         g.nz2 = 1;
-        g.lda = J.nv_a;
+        g.lda = J.kv;
         g.ldb = J.nv;
         g.ldc = J.nv_a;
         g.sAp = J.s_per_p;
@@ -771,7 +781,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         ps.bytes += esz * ((double)pcc * J.s_per_p + (double)pcc * J.nv_a * J.nv_a) +
                     asz * J.part_elems * (first ? 1.0 : 2.0);
         if (first)
-          J.cw = plan_or_tune<E>(ctx, stage, GF_EXCH_W, g, J.rows, J.nv_a, 1, pcc, J.nv_a, true, st);
+          J.cw = plan_or_tune<E>(ctx, stage, GF_EXCH_W, g, J.rows, J.nv_a, 1, pcc, J.kv, true, st);
         else
           stage.add(g, 1, J.cw);
       }
@@ -792,12 +802,12 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.C = w.q.p;
         g.M = J.no_a;
         g.N = J.nvec * J.no_a;
-        g.K = J.nv_a;
+        g.K = J.kv;
         g.np = pcc;
         g.pps = 1;
         g.nz2 = 1;
         g.lda = J.nv;
-        g.ldb = J.nv_a;
+        g.ldb = J.kv;
         g.ldc = (long)J.nvec * J.no_a;
         g.sAp = J.n;
         g.sBp = 0;
@@ -807,7 +817,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         g.order = ORDER_ZIN;
         ps.flops += 2.0 * J.no_a * (double)J.nvec * J.no_a * J.nv_a * pcc;
         ps.bytes += esz * ((double)pcc * J.no_a * J.nv_a + (double)J.nvec * J.no_a * J.nv_a + (double)pcc * J.q_per_p);
-        plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, 1, pcc, J.nv_a, true, st);
+        plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, 1, pcc, J.kv, true, st);
       }
       stage.launch(ctx, GF_EXCH_Q, st);
     }

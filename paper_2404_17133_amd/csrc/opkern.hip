@@ -24,10 +24,13 @@ __device__ inline double from_elem<float>(float v) { return (double)v; }
 template <>
 __device__ inline double from_elem<uint16_t>(uint16_t v) { return (double)bf16_bits_to_f32(v); }
 
-// x (nvec x N, f64) -> xc (nvec x N), xa (nvec x no_a x nv_a), xt (nvec x nv_a x no_a)
+// x (nvec x N, f64) -> xc (nvec x N), xa (nvec x no_a x kv), xt (nvec x kv x no_a): the
+// window [i0, i0 + no_a) x [0, nv_a) of every vector, with the virtual index
+// padded to kv >= nv_a (nv_a <= kv <= nv) by zeros, so that the exchange
+// contractions over it can use 16-byte loads.
 template <typename E>
 __global__ void prep_x_kernel(const double* __restrict__ x, int nvec, int no, int nv, int i0, int no_a,
-                              int nv_a, E* __restrict__ xc, E* __restrict__ xa, E* __restrict__ xt) {
+                              int nv_a, int kv, E* __restrict__ xc, E* __restrict__ xa, E* __restrict__ xt) {
   const long n = (long)no * nv;
   const long total = (long)nvec * n;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
@@ -38,9 +41,10 @@ __global__ void prep_x_kernel(const double* __restrict__ x, int nvec, int no, in
     const E e = to_elem<E>(x[t]);
     if (xc) xc[t] = e;
     const int j = i - i0;
-    if (j >= 0 && j < no_a && a < nv_a) {
-      if (xa) xa[((long)v * no_a + j) * nv_a + a] = e;
-      if (xt) xt[((long)v * nv_a + a) * no_a + j] = e;
+    if (j >= 0 && j < no_a && a < kv) {
+      const E ew = a < nv_a ? e : to_elem<E>(0.0);
+      if (xa) xa[((long)v * no_a + j) * kv + a] = ew;
+      if (xt) xt[((long)v * kv + a) * no_a + j] = ew;
     }
   }
 }
@@ -155,11 +159,12 @@ inline int grid_for(long n, int block = 256) {
 }  // namespace
 
 template <typename E>
-void prep_x(const double* x, int nvec, int no, int nv, int i0, int no_a, int nv_a, E* xc, E* xa, E* xt,
+void prep_x(const double* x, int nvec, int no, int nv, int i0, int no_a, int nv_a, int kv, E* xc, E* xa, E* xt,
             hipStream_t s) {
   const long total = (long)nvec * no * nv;
   if (total == 0) return;
-  hipLaunchKernelGGL(prep_x_kernel<E>, dim3(grid_for(total)), dim3(256), 0, s, x, nvec, no, nv, i0, no_a, nv_a,
+  RID_CHECK(kv >= nv_a && kv <= nv, RID_ERR_INTERNAL, "prep_x: padded window out of range");
+  hipLaunchKernelGGL(prep_x_kernel<E>, dim3(grid_for(total)), dim3(256), 0, s, x, nvec, no, nv, i0, no_a, nv_a, kv,
                      xc, xa, xt);
   RID_HIP(hipGetLastError());
 }
@@ -212,7 +217,7 @@ void transpose_slices(const S* src, int np, int rows, int cols, E* dst, hipStrea
 }
 
 #define RID_INST_E(E)                                                                                   \
-  template void prep_x<E>(const double*, int, int, int, int, int, int, E*, E*, E*, hipStream_t);       \
+  template void prep_x<E>(const double*, int, int, int, int, int, int, int, E*, E*, E*, hipStream_t);  \
   template void coul_bwd<E>(const double*, const E*, int, long, int, double*, hipStream_t);            \
   template void cast_copy<double, E>(const double*, long, E*, hipStream_t);                             \
   template void cast_copy<float, E>(const float*, long, E*, hipStream_t);                               \

@@ -21,7 +21,7 @@ struct CombineArgs {
 };
 
 template <typename E>
-void prep_x(const double* x, int nvec, int no, int nv, int i0, int no_a, int nv_a, E* xc, E* xa, E* xt,
+void prep_x(const double* x, int nvec, int no, int nv, int i0, int no_a, int nv_a, int kv, E* xc, E* xa, E* xt,
             hipStream_t s);
 template <typename A>
 void reduce_splits(const A* part, int ns, long stride, long n, double* out, hipStream_t s);

@@ -584,6 +584,10 @@ struct JobPlan {
   }
   long n = 0, rows = 0, part_elems = 0, s_per_p = 0, q_per_p = 0;
   GemmChoice cw{}, cwp{};
+  // S^P and Q^P of a chunk as one product over the stacked rows (P, i):
+  // possible when the window spans all occupieds, so that those rows of
+  // B_ij and B_ia are evenly spaced.
+  bool stacked() const { return i0 == 0 && no_a == no; }
   int ns_coul = 1;
 };
 
@@ -723,29 +727,41 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         const typename JobPlan<E>::Chunk ck = J.chunk(c);
         const int c0 = ck.c0, pcc = ck.pcc;
         OpWork& w = *J.j->work;
-        // one product per P, run back to back per workgroup (Xt shared)
         GemmParams g{};
-        g.A = ck.ij + (long)c0 * J.no * J.no + (long)J.i0 * J.no + J.i0;
         g.B = w.xt.p;
         g.C = w.s.p;
-        g.M = J.no_a;
         g.N = J.nvec * J.kv;
         g.K = J.no_a;
-        g.np = pcc;
         g.pps = 1;
         g.nz2 = 1;
         g.lda = J.no;
         g.ldb = J.no_a;
         g.ldc = (long)J.nvec * J.kv;
-        g.sAp = (long)J.no * J.no;
         g.sBp = 0;
-        g.sCs = J.s_per_p;
         g.alpha = 1.0;
-        g.mode = GEMM_STORE_EACH;
-        g.order = ORDER_ZIN;  // each XCD keeps its share of Xt in L2 across all P
         ps.flops += 2.0 * J.no_a * (double)J.nvec * J.nv_a * J.no_a * pcc;
         ps.bytes += esz * ((double)pcc * J.no_a * J.no_a + (double)J.nvec * J.nv_a * J.no_a + (double)pcc * J.s_per_p);
-        plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.kv, 1, pcc, J.no_a, true, st);
+        if (J.stacked()) {
+          // all occupieds active: the rows (P, i) of the chunk's B^P_ij are
+          // contiguous, so the chunk is one product with pcc * no rows, and
+          // S^P lands in its per-P layout (no tile padding per P)
+          g.A = ck.ij + (long)c0 * J.no * J.no;
+          g.M = pcc * J.no;
+          g.np = 1;
+          g.mode = GEMM_STORE;
+          g.order = ORDER_MN;
+          plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, g.M, g.N, 1, 1, J.no_a, true, st);
+        } else {
+          // one product per P, run back to back per workgroup (Xt shared)
+          g.A = ck.ij + (long)c0 * J.no * J.no + (long)J.i0 * J.no + J.i0;
+          g.M = J.no_a;
+          g.np = pcc;
+          g.sAp = (long)J.no * J.no;
+          g.sCs = J.s_per_p;
+          g.mode = GEMM_STORE_EACH;
+          g.order = ORDER_ZIN;  // each XCD keeps its share of Xt in L2 across all P
+          plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.kv, 1, pcc, J.no_a, true, st);
+        }
       }
       stage.launch(ctx, GF_EXCH_S, st);
     }
@@ -797,27 +813,37 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         const int c0 = ck.c0, pcc = ck.pcc;
         OpWork& w = *J.j->work;
         GemmParams g{};
-        g.A = ck.ia + (long)c0 * J.n + (long)J.i0 * J.nv;
         g.B = w.xa.p;
         g.C = w.q.p;
-        g.M = J.no_a;
         g.N = J.nvec * J.no_a;
         g.K = J.kv;
-        g.np = pcc;
         g.pps = 1;
         g.nz2 = 1;
         g.lda = J.nv;
         g.ldb = J.kv;
         g.ldc = (long)J.nvec * J.no_a;
-        g.sAp = J.n;
         g.sBp = 0;
-        g.sCs = J.q_per_p;
         g.alpha = 1.0;
-        g.mode = GEMM_STORE_EACH;
-        g.order = ORDER_ZIN;
         ps.flops += 2.0 * J.no_a * (double)J.nvec * J.no_a * J.nv_a * pcc;
         ps.bytes += esz * ((double)pcc * J.no_a * J.nv_a + (double)J.nvec * J.no_a * J.nv_a + (double)pcc * J.q_per_p);
-        plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, 1, pcc, J.kv, true, st);
+        if (J.stacked()) {
+          // rows (P, i) of the chunk's B^P_ia are contiguous: one product
+          g.A = ck.ia + (long)c0 * J.n;
+          g.M = pcc * J.no;
+          g.np = 1;
+          g.mode = GEMM_STORE;
+          g.order = ORDER_MN;
+          plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, g.M, g.N, 1, 1, J.kv, true, st);
+        } else {
+          g.A = ck.ia + (long)c0 * J.n + (long)J.i0 * J.nv;
+          g.M = J.no_a;
+          g.np = pcc;
+          g.sAp = J.n;
+          g.sCs = J.q_per_p;
+          g.mode = GEMM_STORE_EACH;
+          g.order = ORDER_ZIN;
+          plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, 1, pcc, J.kv, true, st);
+        }
       }
       stage.launch(ctx, GF_EXCH_Q, st);
     }

@@ -263,6 +263,7 @@ template <typename E>
 int gemm_slots(int cfg = 0) {
   static const int f64[3] = {256, 512, 256};
   static const int f32[3] = {512, 1024, 512};
+  RID_CHECK(cfg >= 0 && cfg < 3, RID_ERR_INTERNAL, "gemm: bad tile configuration");
   return sizeof(E) == 8 ? f64[cfg] : f32[cfg];
 }
 
@@ -301,8 +302,9 @@ struct GemmChoice {
 // is 1 and nz independent batches run.
 template <typename E>
 GemmChoice plan_for(int cfg, long M, long N, int nz, int np, int K, bool reduction) {
-  static const int bm[3] = {128, 64, 128}, bn[3] = {128, 64, 64};
-  const long tiles = ceil_div_l(M, bm[cfg]) * ceil_div_l(N, bn[cfg]) * nz;
+  int bm = 0, bn = 0;
+  gemm_config_tile<typename GemmTag<E>::type>(cfg, &bm, &bn);
+  const long tiles = ceil_div_l(M, bm) * ceil_div_l(N, bn) * nz;
   if (!reduction) return GemmChoice{cfg, 1, np};
   const SplitPlan sp = choose_splits(tiles, np, K, gemm_slots<E>(cfg));
   return GemmChoice{cfg, sp.nsub, sp.pps};
@@ -346,7 +348,7 @@ GemmChoice tuned(rid_context* ctx, int family, long M, long N, int nz, int np, i
     RID_HIP(hipEventCreate(&b));
     float best_ms = 1e30f;
     GemmChoice last{};
-    for (int cfg = 0; cfg < 3; ++cfg) {
+    for (int cfg = 0; cfg < gemm_num_configs<typename GemmTag<E>::type>(); ++cfg) {
       const GemmChoice ch = plan_for<E>(cfg, M, N, nz, np, K, reduction);
       launch(ch);  // warm
       RID_HIP(hipEventRecord(a, st));
@@ -444,14 +446,18 @@ void launch_members(rid_context* ctx, const std::vector<GemmGroup>& mem, int cfg
 template <typename E>
 struct Stage {
   typedef typename GemmTag<E>::type G;
-  std::vector<GemmGroup> mem[3];
+  static constexpr int kMaxCfgs = 3;  // the most tile configurations of any element type
+  std::vector<GemmGroup> mem[kMaxCfgs];
   void add(const GemmParams& p, int nz, const GemmChoice& ch) {
+    RID_CHECK(ch.cfg >= 0 && ch.cfg < gemm_num_configs<G>() && ch.cfg < kMaxCfgs, RID_ERR_INTERNAL,
+              "gemm: bad tile configuration");
     GemmParams q = p;
     q.pps = ch.pps;
     mem[ch.cfg].push_back(GemmGroup{q, nz, ch.nsub});
   }
   void launch(rid_context* ctx, int family, hipStream_t st) {
-    for (int c = 0; c < 3; ++c) launch_members<G>(ctx, mem[c], c, family, st, gemm_slots<E>(c));
+    for (int c = 0; c < gemm_num_configs<G>() && c < kMaxCfgs; ++c)
+      launch_members<G>(ctx, mem[c], c, family, st, gemm_slots<E>(c));
   }
 };
 
@@ -647,7 +653,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         J.nch_sr = ceil_div(J.nk, J.pc);
         J.nchunks = J.nch_sr + ceil_div(J.nk_lr, J.pc);
         int max_splits = 1;
-        for (int cfg = 0; cfg < 3; ++cfg) {
+        for (int cfg = 0; cfg < gemm_num_configs<typename GemmTag<E>::type>(); ++cfg) {
           max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.kv, true).nsub);
           max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.no_a, true).nsub);
         }

@@ -100,6 +100,21 @@ __global__ void sum_parts_kernel(const double* __restrict__ part, int nch, int m
   C[(long)i * ldc + j] = s;
 }
 
+// The same reduction for few outputs: one wavefront per output, the lanes
+// take the chunks in turn and a fixed butterfly adds their sums, so that a
+// small Gram matrix does not wait on one thread's serial loop.
+__global__ __launch_bounds__(256) void sum_parts_wave_kernel(const double* __restrict__ part, int nch, int m, int n,
+                                                             double* __restrict__ C, int ldc) {
+  const int lane = threadIdx.x & 63;
+  const long t = blockIdx.x * 4L + (threadIdx.x >> 6);
+  if (t >= (long)m * n) return;  // uniform per wavefront
+  const int i = (int)(t / n), j = (int)(t % n);
+  double s = 0.0;
+  for (int c = lane; c < nch; c += 64) s += part[((long)c * m + i) * n + j];
+  s = wave_sum(s);
+  if (lane == 0) C[(long)i * ldc + j] = s;
+}
+
 __global__ __launch_bounds__(256) void norm_part_kernel(const double* __restrict__ W, long ldw, int n, long N,
                                                         long chunk, double* __restrict__ part) {
   const int j = blockIdx.y;
@@ -310,7 +325,10 @@ void gram(const double* V, long ldv, int m, const double* W, long ldw, int n, lo
   dim3 grid((unsigned)ceil_div(m, TI), (unsigned)ceil_div(n, TJ), (unsigned)nch);
   RID_CHECK(ceil_div(m, TI) < 65536 && ceil_div(n, TJ) < 65536, RID_ERR_SHAPE, "gram: too many vectors");
   hipLaunchKernelGGL(gram_part_kernel, grid, dim3(256), 0, s, V, ldv, m, W, ldw, n, N, chunk, rs.part);
-  hipLaunchKernelGGL(sum_parts_kernel, dim3(ceil_div(m * n, 256)), dim3(256), 0, s, rs.part, nch, m, n, C, ldc);
+  if ((long)m * n < 1024)
+    hipLaunchKernelGGL(sum_parts_wave_kernel, dim3(ceil_div(m * n, 4)), dim3(256), 0, s, rs.part, nch, m, n, C, ldc);
+  else
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(ceil_div(m * n, 256)), dim3(256), 0, s, rs.part, nch, m, n, C, ldc);
   RID_HIP(hipGetLastError());
 }
 

@@ -731,6 +731,161 @@ __global__ __launch_bounds__(LB) void lu_lds_kernel(const double* mats, double* 
   for (int i = tid; i < m; i += LB) g[i] = sg[i];
 }
 
+// Blocked right-looking elimination for 128 < m <= LU_BLK_MAX (matrix in
+// global memory, column-major, destroyed).  Per panel of NBK columns: the
+// panel (rows j0..m) is factored in LDS with the same partial pivoting as
+// lu_cm_kernel, the right-hand side (kept in LDS) is eliminated alongside,
+// the panel's row swaps are applied to the trailing columns, the panel rows
+// of the trailing columns are solved with the unit lower factor (U12, also
+// staged in LDS), and the trailing block takes one rank-NBK update spread
+// over all threads.  Every trailing element is read and written once per
+// panel instead of once per column.
+constexpr int LU_BLK_MAX = 512;
+constexpr int NBK = 16;
+
+__device__ inline void block_argmax(double v, int idx, double* rv, int* ri, double& best, int& bi) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  if (lane == 0) {
+    rv[wave] = v;
+    ri[wave] = idx;
+  }
+  __syncthreads();
+  best = -1.0;
+  bi = 1 << 30;
+  for (int w = 0; w < LB / 64; ++w)
+    if (rv[w] > best || (rv[w] == best && ri[w] < bi)) {
+      best = rv[w];
+      bi = ri[w];
+    }
+}
+
+__global__ __launch_bounds__(LB) void lu_blocked_kernel(double* mats, double* rhs, int m) {
+  __shared__ double pan[NBK * LU_BLK_MAX];  // panel: pan[c * m + r], rows r >= j0 used
+  __shared__ double u12[NBK * LU_BLK_MAX];  // panel rows of the trailing columns: u12[c * m + k]
+  __shared__ double sg[LU_BLK_MAX];
+  __shared__ int piv[NBK];
+  __shared__ double rv[LB / 64];
+  __shared__ int ri[LB / 64];
+  double* a = mats + (long)blockIdx.x * m * m;
+  double* g = rhs + (long)blockIdx.x * m;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < m; i += LB) sg[i] = g[i];
+  for (int j0 = 0; j0 < m; j0 += NBK) {
+    const int nb = min(NBK, m - j0);
+    const int k1 = j0 + nb;  // first trailing column
+    // 1. panel to LDS
+    for (int e = tid; e < nb * (m - j0); e += LB) {
+      const int c = e / (m - j0), r = j0 + e % (m - j0);
+      pan[c * m + r] = a[(long)(j0 + c) * m + r];
+    }
+    __syncthreads();
+    // 2. factor the panel (and eliminate the right-hand side)
+    for (int c = 0; c < nb; ++c) {
+      const int j = j0 + c;
+      double v = -1.0;
+      int idx = 1 << 30;
+      for (int i = j + tid; i < m; i += LB) {
+        const double t = fabs(pan[c * m + i]);
+        if (t > v) {
+          v = t;
+          idx = i;
+        }
+      }
+      double best;
+      int p;
+      block_argmax(v, idx, rv, ri, best, p);
+      if (p >= m) p = j;
+      if (tid == 0) piv[c] = p;
+      if (p != j) {
+        for (int cc = tid; cc < nb; cc += LB) {
+          const double t = pan[cc * m + j];
+          pan[cc * m + j] = pan[cc * m + p];
+          pan[cc * m + p] = t;
+        }
+        if (tid == 0) {
+          const double t = sg[j];
+          sg[j] = sg[p];
+          sg[p] = t;
+        }
+      }
+      __syncthreads();
+      const double pv = guard_pivot(pan[c * m + j]);
+      const double gj = sg[j];
+      for (int i = j + 1 + tid; i < m; i += LB) {
+        const double l = pan[c * m + i] / pv;
+        pan[c * m + i] = l;
+        sg[i] -= l * gj;
+      }
+      __syncthreads();
+      // rest of the panel: columns c + 1 .. nb - 1
+      const int r = m - j - 1;
+      for (int e = tid; e < r * (nb - c - 1); e += LB) {
+        const int cc = c + 1 + e / r, i = j + 1 + e % r;
+        pan[cc * m + i] -= pan[c * m + i] * pan[cc * m + j];
+      }
+      __syncthreads();
+    }
+    // 3. panel back to memory
+    for (int e = tid; e < nb * (m - j0); e += LB) {
+      const int c = e / (m - j0), r = j0 + e % (m - j0);
+      a[(long)(j0 + c) * m + r] = pan[c * m + r];
+    }
+    if (k1 < m) {
+      // 4. the panel's row swaps on the trailing columns, in order
+      for (int k = k1 + tid; k < m; k += LB) {
+        double* col = a + (long)k * m;
+        for (int c = 0; c < nb; ++c) {
+          const int p = piv[c];
+          if (p != j0 + c) {
+            const double t = col[j0 + c];
+            col[j0 + c] = col[p];
+            col[p] = t;
+          }
+        }
+        // 5. U12 = L11^{-1} A12 for this column (unit lower triangular)
+        double u[NBK];
+#pragma unroll
+        for (int c = 0; c < NBK; ++c) {
+          if (c < nb) {
+            double t = col[j0 + c];
+            for (int cp = 0; cp < c; ++cp) t -= pan[cp * m + j0 + c] * u[cp];
+            u[c] = t;
+            col[j0 + c] = t;
+            u12[c * m + k] = t;
+          }
+        }
+      }
+      __syncthreads();
+      // 6. trailing update A22 -= L21 U12
+      const int r = m - k1, w = m - k1;
+      for (long e = tid; e < (long)r * w; e += LB) {
+        const int kk = (int)(e / r), i = k1 + (int)(e % r), k = k1 + kk;
+        double t = a[(long)k * m + i];
+        for (int c = 0; c < nb; ++c) t -= pan[c * m + i] * u12[c * m + k];
+        a[(long)k * m + i] = t;
+      }
+    }
+    __syncthreads();
+  }
+  // back substitution with U (diagonal guarded as in the elimination)
+  for (int j = m - 1; j >= 0; --j) {
+    const double yj = sg[j] / guard_pivot(a[(long)j * m + j]);
+    __syncthreads();
+    if (tid == 0) sg[j] = yj;
+    for (int i = tid; i < j; i += LB) sg[i] -= a[(long)j * m + i] * yj;
+    __syncthreads();
+  }
+  for (int i = tid; i < m; i += LB) g[i] = sg[i];
+}
+
 // Pair systems of the inner full-TDDFT solve.  System q of right-hand side
 // b = sys_b[q]: type 0 (shift s != 0): (t- t+ - s^2 I) y = t- g1 + s g2;
 // type 1 (s = 0): t+ y = g1; type 2 (s = 0): t- y' = g2.  Matrices are
@@ -935,6 +1090,8 @@ void small_lu_solve_cm(double* mats, double* rhs, int m, int nb, hipStream_t s) 
   if (m <= 0 || nb <= 0) return;
   if (m <= LU_LDS_MAX)
     hipLaunchKernelGGL(lu_lds_kernel, dim3(nb), dim3(LB), 0, s, mats, rhs, m);
+  else if (m <= LU_BLK_MAX)
+    hipLaunchKernelGGL(lu_blocked_kernel, dim3(nb), dim3(LB), 0, s, mats, rhs, m);
   else
     hipLaunchKernelGGL(lu_cm_kernel, dim3(nb), dim3(LB), 0, s, mats, rhs, m);
   RID_HIP(hipGetLastError());

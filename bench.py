@@ -486,6 +486,8 @@ def main():
     ap.add_argument("--load", type=float, default=0.7, help="serve: arrival rate / saturated rate")
     ap.add_argument("--loads", default=None, help="serve: comma-separated list of loads (overrides --load)")
     ap.add_argument("--fp64", action="store_true", help="serve: also serve the same requests in FP64")
+    ap.add_argument("--concurrent", action="store_true",
+                    help="single: submit the eigen and the polarizability request of a step together")
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent requests")
     ap.add_argument("--hbm-budget-gb", type=int, default=96, help="serve: admission budget")
     args = ap.parse_args()
@@ -530,6 +532,17 @@ def main():
     roots_per_step = k + pm.shape[0]
 
     def step(precision):
+        if args.concurrent:
+            # both requests in one rid_batch_solve: their products share
+            # grouped launches and each one's latency-bound phases overlap
+            # the other's contractions
+            opts = rid.default_opts(args.precond, precision)
+            re_, ke = rid.make_request("eigen", opts, k=k, mode="rpa")
+            ra, ka = rid.make_request("polarizability", opts, p=pm, omegas=[0.0])
+            st_, (e, a) = rid.batch_solve(ctx, [prob, prob], [re_, ra])
+            if st_ != 0 or e["status"] != 0 or a["status"] != 0:
+                raise RuntimeError("batch status %d: %d %d" % (st_, e["status"], a["status"]))
+            return e, a
         e = prob.eigen(k, "rpa", args.precond, precision, vectors=False)
         a = prob.polarizability(pm, [0.0], args.precond, precision)
         if e["status"] != 0 or a["status"] != 0:

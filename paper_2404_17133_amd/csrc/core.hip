@@ -728,7 +728,10 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       reduce_splits<Acc>(w.tpart.as<Acc>(), J.ns_coul, (long)J.nvec * J.naux_j, (long)J.nvec * J.naux_j,
                          w.t64.as<double>(), st);
       w.jbuf.ensure(sizeof(double) * J.nvec * J.n);
-      coul_bwd<E>(w.t64.as<double>(), J.ov.b_ia, J.naux_j, J.n, J.nvec, w.jbuf.as<double>(), st);
+      const int ns = coul_bwd_splits(J.n, J.nvec, J.naux_j);
+      if (ns > 1) w.jpart.ensure(sizeof(double) * (size_t)ns * J.nvec * J.n);
+      coul_bwd<E>(w.t64.as<double>(), J.ov.b_ia, J.naux_j, J.n, J.nvec, w.jbuf.as<double>(),
+                  ns > 1 ? w.jpart.as<double>() : nullptr, ns > 1 ? w.jpart.bytes / sizeof(double) : 0, st);
       ps.flops += 2.0 * J.nvec * J.naux_j * (double)J.n;
       ps.bytes += esz * (double)J.naux_j * J.n * (J.nvec <= 16 ? 1 : ceil_div(J.nvec, 24)) + 8.0 * J.nvec * J.n;
     }

@@ -147,11 +147,12 @@ struct DevBuf {
 
 // Reusable scratch for operator products (grown on demand, never shrunk).
 struct OpWork {
-  DevBuf xc, xa, xt, tpart, t64, jbuf, s, q, wpart, wppart;
-  explicit OpWork(rid_context* c) : xc(c), xa(c), xt(c), tpart(c), t64(c), jbuf(c), s(c), q(c), wpart(c), wppart(c) {}
+  DevBuf xc, xa, xt, tpart, t64, jbuf, jpart, s, q, wpart, wppart;
+  explicit OpWork(rid_context* c)
+      : xc(c), xa(c), xt(c), tpart(c), t64(c), jbuf(c), jpart(c), s(c), q(c), wpart(c), wppart(c) {}
   size_t bytes() const {
-    return xc.bytes + xa.bytes + xt.bytes + tpart.bytes + t64.bytes + jbuf.bytes + s.bytes + q.bytes + wpart.bytes +
-           wppart.bytes;
+    return xc.bytes + xa.bytes + xt.bytes + tpart.bytes + t64.bytes + jbuf.bytes + jpart.bytes + s.bytes + q.bytes +
+           wpart.bytes + wppart.bytes;
   }
 };
 

@@ -60,21 +60,25 @@ __global__ void reduce_splits_kernel(const A* __restrict__ part, int ns, long st
   }
 }
 
-// J[v][ia] = sum_P t[v][P] * b[P][ia]; NVB vectors per blockIdx.y, f64 accumulation.
-// t is read with wave-uniform addresses (scalar loads); b is read once per
-// vector group, coalesced along ia.
+// J[v][ia] = sum_P t[v][P] * b[P][ia]; NVB vectors per blockIdx.y, rows
+// [z * pch, (z + 1) * pch) of P per blockIdx.z, f64 accumulation.  t is read
+// with wave-uniform addresses (scalar loads); b is read once per vector
+// group, coalesced along ia.  With several P ranges each writes its partial
+// sums at out + z * nvec * n (summed afterwards); with one, out is J.
 template <typename E, int NVB>
 __global__ __launch_bounds__(256) void coul_bwd_kernel(const double* __restrict__ t, const E* __restrict__ b,
-                                                       int naux, long n, int nvec, double* __restrict__ j) {
+                                                       int naux, long n, int nvec, int pch, double* __restrict__ out) {
   const long ia = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const int v0 = blockIdx.y * NVB;
+  const int p0 = blockIdx.z * pch, p1 = min(naux, p0 + pch);
+  double* o = out + (long)blockIdx.z * nvec * n;
   double acc[NVB];
 #pragma unroll
   for (int q = 0; q < NVB; ++q) acc[q] = 0.0;
   if (ia < n) {
     // several rows of b in flight per thread: the loop is latency-bound
 #pragma unroll 8
-    for (int p = 0; p < naux; ++p) {
+    for (int p = p0; p < p1; ++p) {
       const double bv = from_elem<E>(b[(long)p * n + ia]);
 #pragma unroll
       for (int q = 0; q < NVB; ++q) {
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(256) void coul_bwd_kernel(const double* __restrict_
     }
 #pragma unroll
     for (int q = 0; q < NVB; ++q)
-      if (v0 + q < nvec) j[(long)(v0 + q) * n + ia] = acc[q];
+      if (v0 + q < nvec) o[(long)(v0 + q) * n + ia] = acc[q];
   }
 }
 
@@ -176,20 +180,37 @@ void reduce_splits(const A* part, int ns, long stride, long n, double* out, hipS
   RID_HIP(hipGetLastError());
 }
 
+int coul_bwd_splits(long n, int nvec, int naux) {
+  // enough workgroups to keep every CU busy with several (b is streamed
+  // once per vector group, so the ranges of P add only partial traffic)
+  const long gx = (n + 255) / 256;
+  const long gy = nvec <= 16 ? 1 : ceil_div(nvec, 24);
+  long ns = (2048 + gx * gy - 1) / (gx * gy);
+  ns = std::min<long>(ns, std::max(1, naux / 64));
+  return (int)std::max<long>(1, std::min<long>(ns, 16));
+}
+
 template <typename E>
-void coul_bwd(const double* t, const E* b, int naux, long n, int nvec, double* j, hipStream_t s) {
+void coul_bwd(const double* t, const E* b, int naux, long n, int nvec, double* j, double* part, size_t part_elems,
+              hipStream_t s) {
   if (n == 0 || nvec == 0) return;
+  int ns = coul_bwd_splits(n, nvec, naux);
+  if (!part || (size_t)ns * nvec * n > part_elems) ns = 1;
+  const int pch = ceil_div(naux, ns);
+  ns = ceil_div(naux, pch);
+  double* out = ns > 1 ? part : j;
   // one pass over b per group of vectors: as few passes as the register
   // budget allows (b is the bulk of the traffic)
   const unsigned gx = (unsigned)((n + 255) / 256);
   if (nvec <= 8)
-    hipLaunchKernelGGL((coul_bwd_kernel<E, 8>), dim3(gx, 1), dim3(256), 0, s, t, b, naux, n, nvec, j);
+    hipLaunchKernelGGL((coul_bwd_kernel<E, 8>), dim3(gx, 1, ns), dim3(256), 0, s, t, b, naux, n, nvec, pch, out);
   else if (nvec <= 16)
-    hipLaunchKernelGGL((coul_bwd_kernel<E, 16>), dim3(gx, 1), dim3(256), 0, s, t, b, naux, n, nvec, j);
+    hipLaunchKernelGGL((coul_bwd_kernel<E, 16>), dim3(gx, 1, ns), dim3(256), 0, s, t, b, naux, n, nvec, pch, out);
   else
-    hipLaunchKernelGGL((coul_bwd_kernel<E, 24>), dim3(gx, (unsigned)ceil_div(nvec, 24)), dim3(256), 0, s, t, b, naux,
-                       n, nvec, j);
+    hipLaunchKernelGGL((coul_bwd_kernel<E, 24>), dim3(gx, (unsigned)ceil_div(nvec, 24), ns), dim3(256), 0, s, t, b,
+                       naux, n, nvec, pch, out);
   RID_HIP(hipGetLastError());
+  if (ns > 1) reduce_splits<double>(part, ns, (long)nvec * n, (long)nvec * n, j, s);
 }
 
 template <typename A>
@@ -218,7 +239,7 @@ void transpose_slices(const S* src, int np, int rows, int cols, E* dst, hipStrea
 
 #define RID_INST_E(E)                                                                                   \
   template void prep_x<E>(const double*, int, int, int, int, int, int, int, E*, E*, E*, hipStream_t);  \
-  template void coul_bwd<E>(const double*, const E*, int, long, int, double*, hipStream_t);            \
+  template void coul_bwd<E>(const double*, const E*, int, long, int, double*, double*, size_t, hipStream_t); \
   template void cast_copy<double, E>(const double*, long, E*, hipStream_t);                             \
   template void cast_copy<float, E>(const float*, long, E*, hipStream_t);                               \
   template void transpose_slices<double, E>(const double*, int, int, int, E*, hipStream_t);             \

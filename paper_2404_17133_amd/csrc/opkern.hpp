@@ -26,7 +26,11 @@ void prep_x(const double* x, int nvec, int no, int nv, int i0, int no_a, int nv_
 template <typename A>
 void reduce_splits(const A* part, int ns, long stride, long n, double* out, hipStream_t s);
 template <typename E>
-void coul_bwd(const double* t, const E* b, int naux, long n, int nvec, double* j, hipStream_t s);
+void coul_bwd(const double* t, const E* b, int naux, long n, int nvec, double* j, double* part, size_t part_elems,
+              hipStream_t s);
+// Ranges of the auxiliary index coul_bwd splits into (its partial buffer
+// holds that many nvec x n blocks; with less it runs unsplit).
+int coul_bwd_splits(long n, int nvec, int naux);
 template <typename A>
 void combine(const CombineArgs& c, const A* wp, const A* wpp, hipStream_t s);
 template <typename S, typename E>

@@ -300,13 +300,20 @@ struct GemmChoice {
 // Tile configuration and split plan of one launch shape.  reduction: the
 // launch sums np batches (split over nsub workgroups per tile); otherwise np
 // is 1 and nz independent batches run.
+//
+// The split plan is the same for every tile configuration (the one that
+// suits the 64x64 tile): a tile's sum over its batches runs in the same
+// order whatever the tile shape, so with a shared plan the tuner's choice of
+// tile, which rests on timings, does not change a single bit of the result,
+// and two runs of the same solve agree exactly.
 template <typename E>
 GemmChoice plan_for(int cfg, long M, long N, int nz, int np, int K, bool reduction) {
-  int bm = 0, bn = 0;
-  gemm_config_tile<typename GemmTag<E>::type>(cfg, &bm, &bn);
-  const long tiles = ceil_div_l(M, bm) * ceil_div_l(N, bn) * nz;
   if (!reduction) return GemmChoice{cfg, 1, np};
-  const SplitPlan sp = choose_splits(tiles, np, K, gemm_slots<E>(cfg));
+  constexpr int ref = 1;  // 64x64
+  int bm = 0, bn = 0;
+  gemm_config_tile<typename GemmTag<E>::type>(ref, &bm, &bn);
+  const long tiles = ceil_div_l(M, bm) * ceil_div_l(N, bn) * nz;
+  const SplitPlan sp = choose_splits(tiles, np, K, gemm_slots<E>(ref));
   return GemmChoice{cfg, sp.nsub, sp.pps};
 }
 

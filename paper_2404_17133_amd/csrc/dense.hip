@@ -406,6 +406,39 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
 }
 
 // Cholesky, left-looking by columns.
+// Cholesky of a small matrix (m <= 64) by one wavefront in LDS, right
+// looking: lane i owns row i.  Same contract as chol_kernel (lower factor in
+// place, upper zeroed, info = first non-positive pivot + 1, such a pivot
+// replaced by 1).  For the block Gram matrices of the orthonormalisation,
+// where the 1024-thread kernel's per-column reductions dominate.
+constexpr int CHOL_SMALL = 64;
+
+__global__ __launch_bounds__(64) void chol_small_kernel(double* a, int m, int lda, int* info) {
+  __shared__ double sa[CHOL_SMALL][CHOL_SMALL + 1];
+  const int i = threadIdx.x;
+  if (i < m)
+    for (int k = 0; k <= i; ++k) sa[i][k] = a[(long)i * lda + k];
+  int bad = 0;
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    const double d = sa[j][j];
+    if (!(d > 0.0) && !bad) bad = j + 1;
+    const double piv = d > 0.0 ? sqrt(d) : 1.0;
+    __syncthreads();  // every lane has read the pivot
+    if (i == j) sa[j][j] = piv;
+    if (i > j && i < m) sa[i][j] /= piv;
+    __syncthreads();
+    if (i > j && i < m) {
+      const double li = sa[i][j];
+      for (int k = j + 1; k <= i; ++k) sa[i][k] -= li * sa[k][j];
+    }
+    __syncthreads();
+  }
+  if (i < m)
+    for (int k = 0; k < m; ++k) a[(long)i * lda + k] = k <= i ? sa[i][k] : 0.0;
+  if (i == 0) info[0] = bad;
+}
+
 __global__ __launch_bounds__(DB) void chol_kernel(double* a, int m, int lda, int* info) {
   __shared__ double red[16];
   __shared__ double piv;
@@ -875,12 +908,31 @@ __global__ __launch_bounds__(LB) void lu_blocked_kernel(double* mats, double* rh
     }
     __syncthreads();
   }
-  // back substitution with U (diagonal guarded as in the elimination)
-  for (int j = m - 1; j >= 0; --j) {
-    const double yj = sg[j] / guard_pivot(a[(long)j * m + j]);
+  // back substitution with U by blocks of NBK rows from the bottom: the
+  // diagonal block is staged in LDS and solved by one thread, then every
+  // thread subtracts the block's columns from its rows above.  Each row
+  // receives its subtractions in the same order (descending columns) as
+  // the column-at-a-time substitution, so the result is bit-identical.
+  for (int j1 = m; j1 > 0; j1 -= NBK) {
+    const int jb = max(0, j1 - NBK), nb = j1 - jb;
+    for (int e = tid; e < nb * nb; e += LB) {
+      const int c = e / nb, r = e - c * nb;
+      pan[c * (NBK + 1) + r] = a[(long)(jb + c) * m + jb + r];
+    }
     __syncthreads();
-    if (tid == 0) sg[j] = yj;
-    for (int i = tid; i < j; i += LB) sg[i] -= a[(long)j * m + i] * yj;
+    if (tid == 0) {
+      for (int r = nb - 1; r >= 0; --r) {
+        double t = sg[jb + r];
+        for (int c = nb - 1; c > r; --c) t -= pan[c * (NBK + 1) + r] * sg[jb + c];
+        sg[jb + r] = t / guard_pivot(pan[r * (NBK + 1) + r]);
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < jb; i += LB) {
+      double t = sg[i];
+      for (int c = nb - 1; c >= 0; --c) t -= a[(long)(jb + c) * m + i] * sg[jb + c];
+      sg[i] = t;
+    }
     __syncthreads();
   }
   for (int i = tid; i < m; i += LB) g[i] = sg[i];
@@ -1076,7 +1128,10 @@ void small_syevx(double* a, int m, int lda, int k, double* w, double* q, int ldq
 
 void small_chol(double* a, int m, int lda, int* info, hipStream_t s) {
   if (m <= 0) return;
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(DB), 0, s, a, m, lda, info);
+  if (m <= CHOL_SMALL)
+    hipLaunchKernelGGL(chol_small_kernel, dim3(1), dim3(64), 0, s, a, m, lda, info);
+  else
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(DB), 0, s, a, m, lda, info);
   RID_HIP(hipGetLastError());
 }
 

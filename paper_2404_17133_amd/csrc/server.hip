@@ -169,7 +169,18 @@ rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const r
     return request_weight(probs[a], reqs[a]) > request_weight(probs[b], reqs[b]);
   });
   const int nworkers = std::min(n, 16);
-  std::atomic<int> next{0};
+  // Two ends of the weight order: even workers take the heaviest request
+  // left, odd workers the lightest.  The heavy solves keep the matrix cores
+  // busy while the light ones, latency-bound, run in their gaps, instead of
+  // all light solves queueing behind the heavy ones and then running on a
+  // device they cannot fill.
+  std::mutex omu;
+  int heavy = 0, light = n - 1;
+  auto take = [&](int w) {
+    std::lock_guard<std::mutex> g(omu);
+    if (heavy > light) return -1;
+    return w % 2 == 0 ? order[heavy++] : order[light--];
+  };
   // admission by estimated footprint against the device memory free at the
   // start (a request too large for the budget runs when it is alone)
   size_t free_b = 0, total_b = 0;
@@ -186,12 +197,11 @@ rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const r
     Batcher batcher(ctx);
     std::vector<std::thread> th;
     for (int w = 0; w < nworkers; ++w)
-      th.emplace_back([&] {
+      th.emplace_back([&, w] {
         try {
           WorkerStream ws(ctx->device);
           const ExecCfg ex{ws.s, &batcher};
-          for (int q = next++; q < n; q = next++) {
-            const int i = order[q];
+          for (int i = take(w); i >= 0; i = take(w)) {
             const uint64_t need = request_footprint(probs[i], reqs[i]);
             {
               std::unique_lock<std::mutex> lk(amu);
@@ -215,7 +225,7 @@ rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const r
         } catch (const Error& e) {
           std::lock_guard<std::mutex> g(g_err_mu);
           ctx->last_error = e.what();
-          for (int q = next++; q < n; q = next++) results[order[q]].status = e.code;
+          for (int i = take(w); i >= 0; i = take(w)) results[i].status = e.code;
         }
       });
     for (std::thread& t : th) t.join();

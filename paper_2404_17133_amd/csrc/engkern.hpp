@@ -69,14 +69,17 @@ void small_eigh(double* a, int m, int lda, double* w, double* q, double* work, h
 size_t small_syevx_work(int m, int k);
 void small_syevx(double* a, int m, int lda, int k, double* w, double* q, int ldq, double* work, hipStream_t s);
 // Cholesky a = L L^T in place (lower triangle, upper zeroed); info[0] = 0 on
-// success, j+1 if the j-th pivot is not positive.
+// success, j+1 if the j-th pivot is not positive (that pivot is replaced by
+// 1 and the factorisation goes on).  One wavefront for m <= 64.
 void small_chol(double* a, int m, int lda, int* info, hipStream_t s);
 // Batched dense solve with partial pivoting: for b < nb, solve
 // M_b y_b = g_b where M_b is m x m at mats + b * m * m (row-major; destroyed)
 // and g_b at rhs + b * m (overwritten by y_b).  A pivot below 1e-300 in
 // magnitude is replaced by +-1e-300.
 void small_lu_solve(double* mats, double* rhs, int m, int nb, hipStream_t s);
-// The same for column-major matrices (faster: two barriers per column).
+// The same for column-major matrices, one workgroup per system: in LDS up
+// to 128 unknowns, by 16-column panels up to 512, a column at a time beyond
+// (the three give bit-identical solutions).
 void small_lu_solve_cm(double* mats, double* rhs, int m, int nb, hipStream_t s);
 // Pair systems of the inner full-TDDFT solve (see dense.hip): build the
 // nsys column-major matrices and right-hand sides, and write the solutions

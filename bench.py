@@ -496,7 +496,7 @@ def main():
         # queueing behind each other (set before the HIP runtime starts)
         os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)

@@ -181,6 +181,8 @@ typedef struct {
   double t_other_ms;     /* projection, small dense, residuals, orthonormalisation */
   double t_total_ms;
   uint64_t bytes_resident; /* device bytes held by the solve at its peak */
+  int32_t n_blocks_cholqr; /* new-direction blocks orthonormalised by two Cholesky-QR passes */
+  int32_t n_blocks_mgs;    /* blocks that took modified Gram-Schmidt (near dependence, drops) */
 } rid_stats;
 
 /* ---- errors ---------------------------------------------------------- */

@@ -81,6 +81,7 @@ class rid_stats(ctypes.Structure):
         ("t_matvec_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
         ("t_other_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double),
         ("bytes_resident", ctypes.c_uint64),
+        ("n_blocks_cholqr", ctypes.c_int32), ("n_blocks_mgs", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -89,7 +90,8 @@ class rid_stats(ctypes.Structure):
                     history=[self.history[i] for i in range(self.n_history)],
                     t_matvec_ms=self.t_matvec_ms, t_precond_ms=self.t_precond_ms,
                     t_other_ms=self.t_other_ms, t_total_ms=self.t_total_ms,
-                    bytes_resident=int(self.bytes_resident))
+                    bytes_resident=int(self.bytes_resident),
+                    n_blocks_cholqr=self.n_blocks_cholqr, n_blocks_mgs=self.n_blocks_mgs)
 
 
 class rid_kernel_stat(ctypes.Structure):
@@ -160,6 +162,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError("librid.so is not built (%s); run `python paper_2404_17133_amd/build.py` "
                           "or __graft_entry__.build()" % path)
+    # The library links the HIP runtime by its soname.  PyTorch ships its own
+    # copy; loading PyTorch first makes the library bind to that same runtime
+    # (one runtime per process).  Loaded the other way round, the process can
+    # end up with two runtimes, and the library then sees no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in PROTOTYPES.items():
         f = getattr(lib, name)

@@ -44,22 +44,6 @@ rid_status guarded(rid_context* ctx, F&& f) {
 
 void use_device(rid_context* ctx) { RID_HIP(hipSetDevice(ctx->device)); }
 
-void fill_stats(rid_stats* out, const rid::SolveStats& s) {
-  if (!out) return;
-  std::memset(out, 0, sizeof(*out));
-  out->n_iter = s.n_iter;
-  out->n_mv = s.n_mv;
-  out->n_inner_mv = s.n_inner_mv;
-  out->n_inner_iter = s.n_inner_iter;
-  out->n_history = (int32_t)std::min<size_t>(s.history.size(), RID_MAX_HISTORY);
-  for (int i = 0; i < out->n_history; ++i) out->history[i] = s.history[i];
-  out->t_matvec_ms = s.t_matvec;
-  out->t_precond_ms = s.t_precond;
-  out->t_total_ms = s.t_total;
-  out->t_other_ms = std::max(0.0, s.t_total - s.t_matvec - s.t_precond);
-  out->bytes_resident = s.peak_bytes;
-}
-
 }  // namespace
 
 extern "C" {

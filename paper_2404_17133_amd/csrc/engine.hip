@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <functional>
 #include <numeric>
 
@@ -228,7 +229,11 @@ int append_orthonormal(Eng& E, Basis& B, double* W, int nnew, double drop_tol = 
     }
   }
   const int m0 = B.m;
-  if (nnew >= 2 && block_cholqr2(E, B, W, nnew, nrm_d)) return nnew;
+  if (nnew >= 2 && block_cholqr2(E, B, W, nnew, nrm_d)) {
+    if (E.stats) ++E.stats->n_blocks_cholqr;
+    return nnew;
+  }
+  if (nnew >= 2 && E.stats) ++E.stats->n_blocks_mgs;
   E.tmp2.ensure(sizeof(double) * (size_t)(nnew + 8));
   double* c = E.tmp2.as<double>();
   for (int j = 0; j < nnew; ++j) {
@@ -1328,6 +1333,24 @@ rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, con
   E.sync();
   st.t_total = ms_since(t_all);
   return status;
+}
+
+void fill_stats(rid_stats* out, const SolveStats& s) {
+  if (!out) return;
+  std::memset(out, 0, sizeof(*out));
+  out->n_iter = s.n_iter;
+  out->n_mv = s.n_mv;
+  out->n_inner_mv = s.n_inner_mv;
+  out->n_inner_iter = s.n_inner_iter;
+  out->n_history = (int32_t)std::min<size_t>(s.history.size(), RID_MAX_HISTORY);
+  for (int i = 0; i < out->n_history; ++i) out->history[i] = s.history[i];
+  out->t_matvec_ms = s.t_matvec;
+  out->t_precond_ms = s.t_precond;
+  out->t_total_ms = s.t_total;
+  out->t_other_ms = std::max(0.0, s.t_total - s.t_matvec - s.t_precond);
+  out->bytes_resident = s.peak_bytes;
+  out->n_blocks_cholqr = s.n_blocks_cholqr;
+  out->n_blocks_mgs = s.n_blocks_mgs;
 }
 
 }  // namespace rid

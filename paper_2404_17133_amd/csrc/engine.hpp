@@ -9,10 +9,14 @@ namespace rid {
 
 struct SolveStats {
   int n_iter = 0, n_mv = 0, n_inner_mv = 0, n_inner_iter = 0;
+  int n_blocks_cholqr = 0, n_blocks_mgs = 0;  // orthonormalisation routes taken
   std::vector<double> history;
   double t_matvec = 0.0, t_precond = 0.0, t_other = 0.0, t_total = 0.0;  // ms
   uint64_t peak_bytes = 0;
 };
+
+// The public statistics of a solve (zeroes out first; out may be null).
+void fill_stats(rid_stats* out, const SolveStats& s);
 
 // Where a solve runs: its stream (null: the context stream) and, for solves
 // that share the device with others, the Batcher that groups their operator

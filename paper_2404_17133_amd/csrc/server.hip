@@ -48,21 +48,7 @@ struct Req {
   uint64_t bytes = 0;
 };
 
-void fill(rid_result* out, const SolveStats& s) {
-  rid_stats& o = out->stats;
-  std::memset(&o, 0, sizeof(o));
-  o.n_iter = s.n_iter;
-  o.n_mv = s.n_mv;
-  o.n_inner_mv = s.n_inner_mv;
-  o.n_inner_iter = s.n_inner_iter;
-  o.n_history = (int)std::min<size_t>(s.history.size(), RID_MAX_HISTORY);
-  for (int i = 0; i < o.n_history; ++i) o.history[i] = s.history[i];
-  o.t_matvec_ms = s.t_matvec;
-  o.t_precond_ms = s.t_precond;
-  o.t_total_ms = s.t_total;
-  o.t_other_ms = std::max(0.0, s.t_total - s.t_matvec - s.t_precond);
-  o.bytes_resident = s.peak_bytes;
-}
+void fill(rid_result* out, const SolveStats& s) { fill_stats(&out->stats, s); }
 
 rid_status run_one(rid_problem* P, const rid_request& r, rid_result* res, const ExecCfg& ex) {
   SolveStats st;

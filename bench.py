@@ -60,10 +60,11 @@ def cpu_baseline(p, n_mv_per_step, roots_per_step, naux_sample=200):
     ops.apply_apb_amb(op, x)  # warm
     t0 = time.perf_counter()
     reps = 0
+    # about 10 s of CPU work (at least 5 repetitions)
     while True:
         ops.apply_apb_amb(op, x)
         reps += 1
-        if time.perf_counter() - t0 > 10.0 or reps >= 20:
+        if (time.perf_counter() - t0 > 10.0 and reps >= 5) or reps >= 400:
             break
     t_slice = (time.perf_counter() - t0) / reps
     t_vec = t_slice * p.naux / naux_sample

@@ -82,10 +82,11 @@ def cpu_baseline(p, n_mv_per_step, roots_per_step, naux_sample=200):
     }
 
 
-def measured_traffic(family: str, dtype: str):
+def measured_traffic(family: str, dtype: str, size: str = "c2"):
     """Calibrated HBM bytes per launch of `family` from the committed counter
-    summary, or None when the GEMM source changed since the counters were
-    taken (or no summary exists)."""
+    summary of the no=200 workload, or None for another workload, when the
+    GEMM source changed since the counters were taken, or when no summary
+    exists."""
     import re
 
     path = os.path.join(ROOT, "profiles", "exch_contractions_c2_mixed_hbm_traffic.md")
@@ -97,6 +98,8 @@ def measured_traffic(family: str, dtype: str):
     text = open(path).read()
     m = re.search(r"GEMM source hash: (\w+)", text)
     if not m or m.group(1) != gemm_source_hash():
+        return None
+    if size != "c2":
         return None
     t = {"f32": "float", "bf16": "bf16_t", "f64": "double"}[dtype]
     fam = family[4:] if family.startswith("ris_") else family
@@ -473,6 +476,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1, help="steps of the FP64 GPU comparison (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--m-max", type=int, default=0,
+                    help="single: subspace size that triggers a restart (0: the library default)")
     ap.add_argument("--size", default="c2", choices=["c1", "c2"],
                     help="single: molecule of the no=100 (c1) or the no=200 (c2, default) workload")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -539,15 +544,16 @@ def main():
             # both requests in one rid_batch_solve: their products share
             # grouped launches and each one's latency-bound phases overlap
             # the other's contractions
-            opts = rid.default_opts(args.precond, precision)
+            opts = rid.default_opts(args.precond, precision, **({"m_max": args.m_max} if args.m_max > 0 else {}))
             re_, ke = rid.make_request("eigen", opts, k=k, mode="rpa")
             ra, ka = rid.make_request("polarizability", opts, p=pm, omegas=[0.0])
             st_, (e, a) = rid.batch_solve(ctx, [prob, prob], [re_, ra])
             if st_ != 0 or e["status"] != 0 or a["status"] != 0:
                 raise RuntimeError("batch status %d: %d %d" % (st_, e["status"], a["status"]))
             return e, a
-        e = prob.eigen(k, "rpa", args.precond, precision, vectors=False)
-        a = prob.polarizability(pm, [0.0], args.precond, precision)
+        kw = {"m_max": args.m_max} if args.m_max > 0 else {}
+        e = prob.eigen(k, "rpa", args.precond, precision, vectors=False, **kw)
+        a = prob.polarizability(pm, [0.0], args.precond, precision, **kw)
         if e["status"] != 0 or a["status"] != 0:
             raise RuntimeError("solve did not converge: %d %d" % (e["status"], a["status"]))
         return e, a
@@ -586,7 +592,7 @@ def main():
     avg_ms = st["ms"] / st["launches"]
     dtype = "f32" if not fam.startswith("ris_") else "bf16"
     achieved = st["flops"] / st["launches"] / (avg_ms * 1e-3) / 1e12
-    traffic = measured_traffic(fam, dtype)
+    traffic = measured_traffic(fam, dtype, args.size)
     roofline = {"bound": "mfma", "kernel": fam, "achieved": round(achieved, 2), "peak": PEAK[dtype],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK[dtype], 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": st["bytes"] / st["launches"],

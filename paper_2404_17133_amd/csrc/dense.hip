@@ -167,6 +167,8 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
                                                    double* work) {
   __shared__ double v[MAXM];
   __shared__ double wv[MAXM];
+  __shared__ double pv[MAXM];  // pending update (absolute index)
+  __shared__ double pw[MAXM];
   __shared__ double part[DB];
   __shared__ double red[16];
   __shared__ double sc[4];
@@ -183,20 +185,34 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
   int* refl = reinterpret_cast<int*>(fp + (long)k * m);  // reflector present flags (m ints)
 
   // ---- 1. tridiagonalisation ------------------------------------------------
+  // Step j reflects column j below the diagonal (v) and would update the
+  // trailing block A_t -= 2 (v w^T + w v^T), w = A_t v - (v^T A_t v) v.
+  // That update is deferred: its vectors are kept (pv, pw, by absolute
+  // index, zero where no update is pending) and applied on the fly where
+  // the next step reads, so each step makes one pass over the trailing block
+  // (apply the pending update, store, accumulate A_t v) instead of two.  The
+  // stored values are the same expressions as an immediate update's, so the
+  // result does not change.
+  for (int i = tid; i < m; i += DB) {
+    pv[i] = 0.0;
+    pw[i] = 0.0;
+  }
+  __syncthreads();
   for (int j = 0; j + 2 < m; ++j) {
     const int n1 = m - j - 1;
     double ss = 0.0;
     for (int r = tid; r < n1; r += DB) {
-      const double x = a[(long)(j + 1 + r) * lda + j];
+      const int R = j + 1 + r;
+      const double x = a[(long)R * lda + j] - 2.0 * (pv[R] * pw[j] + pw[R] * pv[j]);
       v[r] = x;
       ss += x * x;
     }
     ss = block_sum(ss, red);  // includes a barrier after the writes to v
     const double x0 = v[0];
     const double tail = ss - x0 * x0;
-    if (tid == 0) d[j] = a[(long)j * lda + j];
+    if (tid == 0) d[j] = a[(long)j * lda + j] - 2.0 * (pv[j] * pw[j] + pw[j] * pv[j]);
     if (tail <= 1e-300 * (1.0 + ss)) {
-      // column already reduced: no reflector
+      // column already reduced: no reflector (the pending update stays)
       if (tid == 0) {
         e[j] = x0;
         refl[j] = 0;
@@ -218,15 +234,25 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
       refl[j] = 1;
     }
     __syncthreads();
-    // p = A_t v, A_t the trailing block (symmetric): column sums, rows split in R groups
+    // one pass over A_t: apply the pending update, store, and form the
+    // column sums of A_t v (A_t symmetric), rows split in rg groups
     const int cw = ((n1 + 63) / 64) * 64;
     const int rg = max(1, DB / cw);
     {
       const int c = tid % cw, g = tid / cw;
       if (g < rg) {
         double acc = 0.0;
-        if (c < n1)
-          for (int r = g; r < n1; r += rg) acc += a[(long)(j + 1 + r) * lda + (j + 1 + c)] * v[r];
+        if (c < n1) {
+          const int C = j + 1 + c;
+          const double pvc = pv[C], pwc = pw[C];
+          for (int r = g; r < n1; r += rg) {
+            const int R = j + 1 + r;
+            double* ap = a + (long)R * lda + C;
+            const double val = *ap - 2.0 * (pv[R] * pwc + pw[R] * pvc);
+            *ap = val;
+            acc += val * v[r];
+          }
+        }
         part[g * cw + c] = acc;
       }
     }
@@ -239,26 +265,24 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
       kp += pc * v[c];
     }
     kp = block_sum(kp, red);  // barrier: wv complete
-    for (int c = tid; c < n1; c += DB) wv[c] -= kp * v[c];
-    __syncthreads();
-    // A_t -= 2 (v w^T + w v^T)
-    for (long idx = tid; idx < (long)n1 * n1; idx += DB) {
-      const int r = (int)(idx / n1), c = (int)(idx - (long)r * n1);
-      a[(long)(j + 1 + r) * lda + (j + 1 + c)] -= 2.0 * (v[r] * wv[c] + wv[r] * v[c]);
+    // this step's update becomes the pending one
+    for (int c = tid; c < n1; c += DB) {
+      pv[j + 1 + c] = v[c];
+      pw[j + 1 + c] = wv[c] - kp * v[c];
     }
     __syncthreads();
   }
   if (tid == 0) {
     if (m >= 2) {
-      d[m - 2] = a[(long)(m - 2) * lda + (m - 2)];
-      e[m - 2] = a[(long)(m - 1) * lda + (m - 2)];
+      d[m - 2] = a[(long)(m - 2) * lda + (m - 2)] - 2.0 * (pv[m - 2] * pw[m - 2] + pw[m - 2] * pv[m - 2]);
+      e[m - 2] = a[(long)(m - 1) * lda + (m - 2)] - 2.0 * (pv[m - 1] * pw[m - 2] + pw[m - 1] * pv[m - 2]);
       if (m - 2 >= 0) refl[m - 2] = 0;
     }
-    d[m - 1] = a[(long)(m - 1) * lda + (m - 1)];
+    d[m - 1] = a[(long)(m - 1) * lda + (m - 1)] - 2.0 * (pv[m - 1] * pw[m - 1] + pw[m - 1] * pv[m - 1]);
     e[m - 1] = 0.0;
     refl[m - 1] = 0;
   }
-  __syncthreads();
+  __syncthreads();  // d, e and refl are read by every thread below
   // ---- 2. bisection -----------------------------------------------------------
   double tn = 0.0;
   for (int i = tid; i < m; i += DB) {

@@ -495,6 +495,98 @@ __global__ __launch_bounds__(DB) void chol_kernel(double* a, int m, int lda, int
   if (tid == 0) info[0] = bad;
 }
 
+// Cholesky by panels of NBC columns, right looking (64 < m <= 512).  The
+// panel (its rows j0..m-1) is factored column by column in LDS, written
+// back, and then applied to the trailing lower triangle as one rank-NBC
+// update: lanes run along a row of the trailing block (coalesced), each
+// holding the panel entries of its own column in registers, and the panel
+// row of the output row is read by all lanes at once.  Every trailing
+// element is read and written once per panel; the column-wise kernel above
+// instead walks each row in a separate thread, with every load spread over
+// 64 rows.  Same contract as chol_kernel.
+constexpr int CHOL_BLK_MAX = 512;
+constexpr int NBC = 16;
+
+__global__ __launch_bounds__(DB) void chol_blocked_kernel(double* a, int m, int lda, int* info) {
+  __shared__ double pan[CHOL_BLK_MAX * (NBC + 1)];  // pan[r * (NBC + 1) + c], row r counted from j0
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int bad = 0;  // meaningful in thread 0
+  for (int j0 = 0; j0 < m; j0 += NBC) {
+    const int nb = min(NBC, m - j0);
+    const int rows = m - j0;
+    // 1. panel to LDS (entries above the diagonal are loaded but never used)
+    for (int e = tid; e < rows * nb; e += DB) {
+      const int r = e / nb, c = e - r * nb;
+      pan[r * (NBC + 1) + c] = a[(long)(j0 + r) * lda + j0 + c];
+    }
+    __syncthreads();
+    // 2. factor the panel
+    for (int c = 0; c < nb; ++c) {
+      const double d = pan[c * (NBC + 1) + c];
+      __syncthreads();  // every thread has read the pivot
+      if (tid == 0 && !(d > 0.0) && !bad) bad = j0 + c + 1;
+      const double piv = d > 0.0 ? sqrt(d) : 1.0;
+      for (int r = c + tid; r < rows; r += DB) pan[r * (NBC + 1) + c] = r == c ? piv : pan[r * (NBC + 1) + c] / piv;
+      __syncthreads();
+      const int w = nb - c - 1;
+      for (int e = tid; e < (rows - c - 1) * w; e += DB) {
+        const int r = c + 1 + e / w, c2 = c + 1 + e % w;
+        if (c2 <= r) pan[r * (NBC + 1) + c2] -= pan[r * (NBC + 1) + c] * pan[c2 * (NBC + 1) + c];
+      }
+      __syncthreads();
+    }
+    // 3. panel back to memory (lower part)
+    for (int e = tid; e < rows * nb; e += DB) {
+      const int r = e / nb, c = e - r * nb;
+      if (c <= r) a[(long)(j0 + r) * lda + j0 + c] = pan[r * (NBC + 1) + c];
+    }
+    // 4. trailing update A22 -= L21 L21^T on the lower triangle.  A trailing
+    // block exists only when this panel is full (nb == NBC).
+    const int k1 = j0 + nb, mt = m - k1;
+    if (mt > 0) {
+      const int bands = (mt + 63) / 64;       // 64-column bands, at most 8
+      const int rg = max(1, (DB / 64) / bands);  // waves per band, split over rows
+      const int band = wave % bands, g = wave / bands;
+      if (g < rg) {
+        const int kc = band * 64 + lane;  // column in the trailing block
+        double lk[NBC];
+#pragma unroll
+        for (int p = 0; p < NBC; ++p) lk[p] = kc < mt ? pan[(nb + kc) * (NBC + 1) + p] : 0.0;
+        for (int i0 = band * 64 + g; i0 < mt; i0 += 4 * rg) {
+          double av[4], t[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * rg;
+            av[u] = (kc < mt && i < mt && kc <= i) ? a[(long)(k1 + i) * lda + k1 + kc] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * rg;
+            double s = 0.0;
+            if (i < mt) {
+              const double* pr = pan + (nb + i) * (NBC + 1);
+#pragma unroll
+              for (int p = 0; p < NBC; ++p) s += pr[p] * lk[p];
+            }
+            t[u] = s;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * rg;
+            if (kc < mt && i < mt && kc <= i) a[(long)(k1 + i) * lda + k1 + kc] = av[u] - t[u];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < m * m; t += DB) {
+    const int i = t / m, j = t - i * m;
+    if (j > i) a[(long)i * lda + j] = 0.0;
+  }
+  if (tid == 0) info[0] = bad;
+}
+
 // Gaussian elimination with partial pivoting, one system per workgroup.
 __global__ __launch_bounds__(DB) void lu_solve_kernel(double* mats, double* rhs, int m) {
   __shared__ double rv[16];
@@ -1154,6 +1246,8 @@ void small_chol(double* a, int m, int lda, int* info, hipStream_t s) {
   if (m <= 0) return;
   if (m <= CHOL_SMALL)
     hipLaunchKernelGGL(chol_small_kernel, dim3(1), dim3(64), 0, s, a, m, lda, info);
+  else if (m <= CHOL_BLK_MAX)
+    hipLaunchKernelGGL(chol_blocked_kernel, dim3(1), dim3(DB), 0, s, a, m, lda, info);
   else
     hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(DB), 0, s, a, m, lda, info);
   RID_HIP(hipGetLastError());

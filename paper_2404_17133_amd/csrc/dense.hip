@@ -175,9 +175,9 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* d = work;
   double* e = work + m;
-  double* e2 = work + 2 * m;
+  // work[2m, 3m) is unused (kept so the layout stays put)
   double* y = work + 3 * m;              // k vectors of length m
-  double* fu = y + (long)k * m;          // factor storage per vector: u, s1, s2, l, piv
+  double* fu = y + (long)k * m;          // factors u, s1, s2, l, piv: entry i of vector t at [i * k + t]
   double* fs1 = fu + (long)k * m;
   double* fs2 = fs1 + (long)k * m;
   double* fl = fs2 + (long)k * m;
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
     for (int r = tid; r < n1; r += DB) {
       const double vr = (r == 0 ? x0 - alpha : v[r]) / vn;
       v[r] = vr;
-      a[(long)(j + 1 + r) * lda + j] = vr;  // keep the reflector for the back-transformation
+      a[(long)j * lda + j + 1 + r] = vr;  // reflector kept in row j above the diagonal (unused from here on)
     }
     if (tid == 0) {
       e[j] = alpha;
@@ -283,13 +283,17 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
     refl[m - 1] = 0;
   }
   __syncthreads();  // d, e and refl are read by every thread below
-  // ---- 2. bisection -----------------------------------------------------------
+  // ---- 2. eigenvalues of T by multisection ----------------------------------
+  // Wave t brackets eigenvalue t (and t + 16, ...): its 64 lanes take Sturm
+  // counts at 64 interior points of the bracket, which shrinks it 65-fold per
+  // step, until its width is at the rounding level of the eigenvalue or of
+  // ||T|| (the accuracy the counts support).  d and e^2 are staged in LDS.
   double tn = 0.0;
   for (int i = tid; i < m; i += DB) {
-    e2[i] = e[i] * e[i];
+    v[i] = d[i];
+    wv[i] = e[i] * e[i];
     tn = fmax(tn, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
   }
-  // max reduction through the sum helper on squared-free values: use a wave max
   for (int o = 32; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, 64));
   __syncthreads();
   if (lane == 0) red[wave] = tn;
@@ -302,32 +306,37 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
   __syncthreads();
   const double tnorm = fmax(sc[0], 1e-300);
   const double pivmin = 1e-300 + 1e-30 * tnorm * tnorm;
-  if (tid < k) {
+  const double atol = 2.2e-16 * tnorm;
+  for (int t = wave; t < k; t += DB / 64) {
     double lo = -tnorm, hi = tnorm;
-    for (int it = 0; it < 200; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.2e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
-      if (sturm_count(d, e2, m, mid, pivmin) > tid)
-        hi = mid;
-      else
-        lo = mid;
+    for (int it = 0; it < 64; ++it) {
+      const double wid = hi - lo;
+      if (wid <= 2.2e-16 * fmax(fabs(lo), fabs(hi)) + atol) break;
+      const double x = lo + wid * (double)(lane + 1) / 65.0;
+      const unsigned long long above = __ballot(sturm_count(v, wv, m, x, pivmin) > t);
+      if (above == 0ull) {
+        lo = lo + wid * 64.0 / 65.0;
+      } else {
+        const int f = __ffsll(above) - 1;  // first point above eigenvalue t
+        const double nlo = f > 0 ? lo + wid * (double)f / 65.0 : lo;
+        hi = lo + wid * (double)(f + 1) / 65.0;
+        lo = nlo;
+      }
     }
-    w[tid] = 0.5 * (lo + hi);
+    if (lane == 0) w[t] = 0.5 * (lo + hi);
   }
   __syncthreads();
   // ---- 3. inverse iteration ---------------------------------------------------
   // factor T - lambda_t I with partial pivoting (thread t), rows i, i+1 swapped
   // when |e_i| > |u_i|; u diagonal, s1/s2 the two superdiagonals, l multipliers.
+  // The factors of the k shifts are interleaved (entry i of all shifts
+  // adjacent), so the threads' loads are contiguous.
   if (tid < k) {
     const double lam = w[tid];
-    double* u = fu + (long)tid * m;
-    double* s1 = fs1 + (long)tid * m;
-    double* s2 = fs2 + (long)tid * m;
-    double* l = fl + (long)tid * m;
-    double* pv = fp + (long)tid * m;
     const double eps_piv = 2.2e-16 * tnorm;
     double di = d[0] - lam, ci = m > 1 ? e[0] : 0.0;  // current row: diag, super
     for (int i = 0; i < m - 1; ++i) {
+      const long at = (long)i * k + tid;
       const double bi = e[i];                // subdiagonal below the current row
       const double dn = d[i + 1] - lam;       // next row diag
       const double cn = (i + 1 < m - 1) ? e[i + 1] : 0.0;  // next row super
@@ -335,80 +344,91 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
         // no swap: eliminate next row with the current one
         const double piv = fabs(di) < eps_piv ? (di < 0 ? -eps_piv : eps_piv) : di;
         const double mult = bi / piv;
-        u[i] = piv;
-        s1[i] = ci;
-        s2[i] = 0.0;
-        l[i] = mult;
-        pv[i] = 0.0;
+        fu[at] = piv;
+        fs1[at] = ci;
+        fs2[at] = 0.0;
+        fl[at] = mult;
+        fp[at] = 0.0;
         di = dn - mult * ci;
         ci = cn;
       } else {
         // swap rows i and i+1
         const double mult = di / bi;
-        u[i] = bi;
-        s1[i] = dn;
-        s2[i] = cn;
-        l[i] = mult;
-        pv[i] = 1.0;
+        fu[at] = bi;
+        fs1[at] = dn;
+        fs2[at] = cn;
+        fl[at] = mult;
+        fp[at] = 1.0;
         di = ci - mult * dn;
         ci = -mult * cn;
       }
     }
-    u[m - 1] = fabs(di) < eps_piv ? (di < 0 ? -eps_piv : eps_piv) : di;
+    fu[(long)(m - 1) * k + tid] = fabs(di) < eps_piv ? (di < 0 ? -eps_piv : eps_piv) : di;
     // starting vector: deterministic, not orthogonal to any eigenvector in practice
     double* yt = y + (long)tid * m;
     for (int i = 0; i < m; ++i) yt[i] = 1.0 + 0.01 * (double)((i * 7919 + tid * 104729) % 101) / 101.0;
   }
   __syncthreads();
+  // clusters of close eigenvalues (consecutive gaps <= 1e-3 ||T||): cluster c
+  // is handled by wave c mod 16, which orthogonalises its vectors in
+  // ascending order; other waves never touch them, so no block barrier is
+  // needed between vectors.
+  const double gap = 1e-3 * tnorm;
   for (int iter = 0; iter < 4; ++iter) {
     if (tid < k) {
-      const double* u = fu + (long)tid * m;
-      const double* s1 = fs1 + (long)tid * m;
-      const double* s2 = fs2 + (long)tid * m;
-      const double* l = fl + (long)tid * m;
-      const double* pv = fp + (long)tid * m;
       double* yt = y + (long)tid * m;
-      // forward: apply the row interchanges and multipliers
+      // forward: row interchanges and multipliers (y_i carried in yc)
+      double yc = yt[0];
+#pragma unroll 4
       for (int i = 0; i < m - 1; ++i) {
-        if (pv[i] != 0.0) {
-          const double t = yt[i];
-          yt[i] = yt[i + 1];
-          yt[i + 1] = t - l[i] * yt[i];
+        const long at = (long)i * k + tid;
+        const double yn = yt[i + 1];
+        if (fp[at] != 0.0) {
+          yt[i] = yn;
+          yc = yc - fl[at] * yn;
         } else {
-          yt[i + 1] -= l[i] * yt[i];
+          yt[i] = yc;
+          yc = yn - fl[at] * yc;
         }
       }
-      // backward: upper triangular with two superdiagonals
+      yt[m - 1] = yc;
+      // backward: upper triangular with two superdiagonals (y_{i+1}, y_{i+2}
+      // carried in y1, y2)
+      double y1 = 0.0, y2 = 0.0;
+#pragma unroll 4
       for (int i = m - 1; i >= 0; --i) {
+        const long at = (long)i * k + tid;
         double t = yt[i];
-        if (i + 1 < m) t -= s1[i] * yt[i + 1];
-        if (i + 2 < m) t -= s2[i] * yt[i + 2];
-        yt[i] = t / u[i];
+        if (i + 1 < m) t -= fs1[at] * y1;
+        if (i + 2 < m) t -= fs2[at] * y2;
+        const double yi = t / fu[at];
+        yt[i] = yi;
+        y2 = y1;
+        y1 = yi;
       }
     }
     __syncthreads();
-    // normalise and re-orthogonalise within clusters, in ascending order
+    int cl = -1;
     for (int t = 0; t < k; ++t) {
-      double* yt = y + (long)t * m;
-      const double lt = w[t];
+      if (t == 0 || fabs(w[t - 1] - w[t]) > gap) ++cl;  // t starts cluster cl
+      if (cl % (DB / 64) != wave) continue;
       int t0 = t;
-      while (t0 > 0 && fabs(w[t0 - 1] - w[t0]) <= 1e-3 * tnorm) --t0;
-      for (int s = t0; s < t; ++s) {
-        const double* ys = y + (long)s * m;
+      while (t0 > 0 && fabs(w[t0 - 1] - w[t0]) <= gap) --t0;
+      double* yt = y + (long)t * m;
+      for (int s2 = t0; s2 < t; ++s2) {
+        const double* ys = y + (long)s2 * m;
         double dp = 0.0;
-        for (int i = tid; i < m; i += DB) dp += ys[i] * yt[i];
-        dp = block_sum(dp, red);
-        for (int i = tid; i < m; i += DB) yt[i] -= dp * ys[i];
-        __syncthreads();
+        for (int i = lane; i < m; i += 64) dp += ys[i] * yt[i];
+        dp = wave_sum(dp);
+        for (int i = lane; i < m; i += 64) yt[i] -= dp * ys[i];
       }
       double nn = 0.0;
-      for (int i = tid; i < m; i += DB) nn += yt[i] * yt[i];
-      nn = block_sum(nn, red);
+      for (int i = lane; i < m; i += 64) nn += yt[i] * yt[i];
+      nn = wave_sum(nn);
       const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-      for (int i = tid; i < m; i += DB) yt[i] *= inv;
-      __syncthreads();
-      (void)lt;
+      for (int i = lane; i < m; i += 64) yt[i] *= inv;
     }
+    __syncthreads();
   }
   // ---- 4. back-transformation, one wave per vector ----------------------------
   for (int t = wave; t < k; t += DB / 64) {
@@ -417,9 +437,10 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
       if (!refl[j]) continue;
       const int n1 = m - j - 1;
       double dp = 0.0;
-      for (int r = lane; r < n1; r += 64) dp += a[(long)(j + 1 + r) * lda + j] * yt[j + 1 + r];
+      const double* hv = a + (long)j * lda + j + 1;
+      for (int r = lane; r < n1; r += 64) dp += hv[r] * yt[j + 1 + r];
       dp = wave_sum(dp);
-      for (int r = lane; r < n1; r += 64) yt[j + 1 + r] -= 2.0 * dp * a[(long)(j + 1 + r) * lda + j];
+      for (int r = lane; r < n1; r += 64) yt[j + 1 + r] -= 2.0 * dp * hv[r];
     }
   }
   __syncthreads();

@@ -163,6 +163,8 @@ __device__ inline int sturm_count(const double* __restrict__ d, const double* __
   return cnt;
 }
 
+constexpr int SYEVX_YLDS = 8192;  // inverse-iteration vectors held in LDS up to k * m = 8192
+
 __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, int k, double* w, double* q, int ldq,
                                                    double* work) {
   __shared__ double v[MAXM];
@@ -172,12 +174,14 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
   __shared__ double part[DB];
   __shared__ double red[16];
   __shared__ double sc[4];
+  __shared__ double ylds[SYEVX_YLDS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* d = work;
   double* e = work + m;
   // work[2m, 3m) is unused (kept so the layout stays put)
-  double* y = work + 3 * m;              // k vectors of length m
-  double* fu = y + (long)k * m;          // factors u, s1, s2, l, piv: entry i of vector t at [i * k + t]
+  // k vectors of length m, in LDS when they fit (the work slot is then unused)
+  double* y = (long)k * m <= SYEVX_YLDS ? ylds : work + 3 * m;
+  double* fu = work + 3 * m + (long)k * m;  // factors u, s1, s2, l, piv: entry i of vector t at [i * k + t]
   double* fs1 = fu + (long)k * m;
   double* fs2 = fs1 + (long)k * m;
   double* fl = fs2 + (long)k * m;
@@ -431,16 +435,35 @@ __global__ __launch_bounds__(DB) void syevx_kernel(double* a, int m, int lda, in
     __syncthreads();
   }
   // ---- 4. back-transformation, one wave per vector ----------------------------
+  // y <- H_0 ... H_{m-3} y with the vector in registers (entry i in lane
+  // i % 64, slot i / 64); reflector j is row j of a right of the diagonal.
   for (int t = wave; t < k; t += DB / 64) {
     double* yt = y + (long)t * m;
+    double yr[MAXM / 64];
+#pragma unroll
+    for (int sl = 0; sl < MAXM / 64; ++sl) {
+      const int i = sl * 64 + lane;
+      yr[sl] = i < m ? yt[i] : 0.0;
+    }
     for (int j = m - 3; j >= 0; --j) {
       if (!refl[j]) continue;
-      const int n1 = m - j - 1;
+      const double* hrow = a + (long)j * lda;
+      double h[MAXM / 64];
       double dp = 0.0;
-      const double* hv = a + (long)j * lda + j + 1;
-      for (int r = lane; r < n1; r += 64) dp += hv[r] * yt[j + 1 + r];
+#pragma unroll
+      for (int sl = 0; sl < MAXM / 64; ++sl) {
+        const int i = sl * 64 + lane;
+        h[sl] = (i > j && i < m) ? hrow[i] : 0.0;
+        dp += h[sl] * yr[sl];
+      }
       dp = wave_sum(dp);
-      for (int r = lane; r < n1; r += 64) yt[j + 1 + r] -= 2.0 * dp * hv[r];
+#pragma unroll
+      for (int sl = 0; sl < MAXM / 64; ++sl) yr[sl] -= 2.0 * dp * h[sl];
+    }
+#pragma unroll
+    for (int sl = 0; sl < MAXM / 64; ++sl) {
+      const int i = sl * 64 + lane;
+      if (i < m) yt[i] = yr[sl];
     }
   }
   __syncthreads();

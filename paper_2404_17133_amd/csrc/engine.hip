@@ -148,6 +148,23 @@ struct Basis {
   uint64_t bytes() const { return v.bytes + p1.bytes + p2.bytes + a1.bytes + a2.bytes; }
 };
 
+// Copies columns n (length N, stride N) of src to dst for every n with
+// done[n] == 0, one copy per run of consecutive such columns.
+void copy_open_columns(const std::vector<char>& done, const double* src, double* dst, long N, hipStream_t st) {
+  const int nr = (int)done.size();
+  for (int n = 0; n < nr;) {
+    if (done[n]) {
+      ++n;
+      continue;
+    }
+    int e = n + 1;
+    while (e < nr && !done[e]) ++e;
+    RID_HIP(hipMemcpyAsync(dst + (long)n * N, src + (long)n * N, sizeof(double) * (size_t)(e - n) * N,
+                           hipMemcpyDeviceToDevice, st));
+    n = e;
+  }
+}
+
 // Orthonormalise nnew directions W (row-major, ld N; overwritten) against the
 // basis and each other, append the accepted ones.  Returns the number added.
 // Every step runs on the device.  After the projection against the basis,
@@ -170,26 +187,24 @@ constexpr double kCholQrMinPivot = 1e-3;
 bool block_cholqr2(Eng& E, Basis& B, double* W, int n, const double* nrm_d) {
   const long N = E.N;
   const int m0 = B.m;
-  E.tmp2.ensure(sizeof(double) * (size_t)(2 * n * n + 8));
+  E.tmp2.ensure(sizeof(double) * (size_t)(2 * n * n + 2 * n + 8));
   E.ints.ensure(sizeof(int) * 2);
   double* G = E.tmp2.as<double>();
   double* Li = G + (size_t)n * n;
+  double* chk = Li + (size_t)n * n;  // diag(L), initial norms, info
   int* info = E.ints.as<int>();
   {
     RedScratch rs = E.rs(n, n);
     gram(W, N, n, W, N, n, N, G, n, rs, E.st);
   }
   small_chol(G, n, n, info, E.st);
-  std::vector<double> hl((size_t)n * n), hn(n);
-  int hinfo = 1;
-  RID_HIP(hipMemcpyAsync(hl.data(), G, sizeof(double) * n * n, hipMemcpyDeviceToHost, E.st));
-  RID_HIP(hipMemcpyAsync(hn.data(), nrm_d, sizeof(double) * n, hipMemcpyDeviceToHost, E.st));
-  RID_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, E.st));
-  E.sync();
-  if (hinfo != 0) return false;
+  chol_check_pack(G, n, n, nrm_d, info, chk, E.st);
+  std::vector<double> hc(2 * (size_t)n + 1);
+  E.d2h(hc.data(), chk, sizeof(double) * hc.size());
+  if (hc[2 * n] != 0.0) return false;
   for (int j = 0; j < n; ++j) {
-    const double d = hl[(size_t)j * n + j];
-    if (!std::isfinite(hn[j]) || hn[j] == 0.0 || !std::isfinite(d) || !(d >= kCholQrMinPivot)) return false;
+    const double d = hc[j], nj = hc[n + j];
+    if (!std::isfinite(nj) || nj == 0.0 || !std::isfinite(d) || !(d >= kCholQrMinPivot)) return false;
   }
   // first pass into the basis slots, second pass back into W, then copy
   small_trinv_lower(G, n, n, Li, n, E.st);
@@ -470,12 +485,11 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
       col_norms(rho.as<double>(), N, nr, N, rnd.as<double>(), rs, E.st);
     }
     E.d2h(rhon.data(), rnd.as<double>(), sizeof(double) * nr);
+    // freeze the solution of every right-hand side still open at its latest iterate
+    copy_open_columns(done, sol.as<double>(), out, N, E.st);
     std::vector<int> act;
     for (int n = 0; n < nr; ++n) {
       if (done[n]) continue;
-      // freeze the solution of this right-hand side at its latest iterate
-      RID_HIP(hipMemcpyAsync(out + (long)n * N, sol.as<double>() + (long)n * N, sizeof(double) * N,
-                             hipMemcpyDeviceToDevice, E.st));
       if (rhon[n] < tol)
         done[n] = 1;
       else
@@ -633,13 +647,11 @@ InnerResult inner_pair(Eng& E, int prec, const double* r1, const double* r2, int
       col_norms(rho2.as<double>(), N, nr, N, rnd.as<double>() + nr, rs, E.st);
     }
     E.d2h(rr.data(), rnd.as<double>(), sizeof(double) * 2 * nr);
+    copy_open_columns(done, s1.as<double>(), out1, N, E.st);
+    copy_open_columns(done, s2.as<double>(), out2, N, E.st);
     std::vector<int> act;
     for (int n = 0; n < nr; ++n) {
       if (done[n]) continue;
-      RID_HIP(hipMemcpyAsync(out1 + (long)n * N, s1.as<double>() + (long)n * N, sizeof(double) * N,
-                             hipMemcpyDeviceToDevice, E.st));
-      RID_HIP(hipMemcpyAsync(out2 + (long)n * N, s2.as<double>() + (long)n * N, sizeof(double) * N,
-                             hipMemcpyDeviceToDevice, E.st));
       if (std::sqrt(rr[n] * rr[n] + rr[nr + n] * rr[nr + n]) < tol)
         done[n] = 1;
       else

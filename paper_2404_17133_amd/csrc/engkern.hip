@@ -306,7 +306,23 @@ __global__ void accept_scale_kernel(const double* __restrict__ src, long n, cons
     dst[t] = ok ? alpha * src[t] : 0.0;
 }
 
+__global__ void chol_check_pack_kernel(const double* __restrict__ l, int n, int ldl, const double* __restrict__ nrm,
+                                       const int* __restrict__ info, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    out[t] = l[(long)t * ldl + t];
+    out[n + t] = nrm[t];
+  }
+  if (t == 0) out[2 * n] = (double)info[0];
+}
+
 }  // namespace
+
+void chol_check_pack(const double* l, int n, int ldl, const double* nrm, const int* info, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(chol_check_pack_kernel, dim3((n + 255) / 256), dim3(256), 0, s, l, n, ldl, nrm, info, out);
+  RID_HIP(hipGetLastError());
+}
 
 void accept_scale(const double* src, long n, const double* r, double tol, double* dst, hipStream_t s) {
   if (n <= 0) return;

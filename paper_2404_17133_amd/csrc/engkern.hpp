@@ -57,6 +57,9 @@ void unit_vectors(const int* pos, int n, long N, double* out, long ldo, hipStrea
 void scale_copy(const double* src, long n, double alpha, double* dst, hipStream_t s);
 // dst = src / r if the device scalar r >= tol, else 0.
 void accept_scale(const double* src, long n, const double* r, double tol, double* dst, hipStream_t s);
+// out[0, n) = diagonal of l (n x n, leading dim ldl), out[n, 2n) = nrm[0, n),
+// out[2n] = info[0]: the figures a Cholesky-QR step checks, for one read.
+void chol_check_pack(const double* l, int n, int ldl, const double* nrm, const int* info, double* out, hipStream_t s);
 
 // ---- small dense FP64 (dense.hip) -------------------------------------------
 // Symmetric eigen-decomposition of a (m x m, leading dim lda) by cyclic

@@ -906,11 +906,21 @@ __global__ __launch_bounds__(LB) void lu_lds_kernel(const double* mats, double* 
     }
     __syncthreads();
     // trailing update, element (i, k) of the (m-j-1)^2 block per thread
+    // (linear index e = kk r + ii stepped without a division per element)
     const int r = m - j - 1;
-    for (int e = tid; e < r * r; e += LB) {
-      const int kk = e / r, ii = e - kk * r;
-      const int i = j + 1 + ii, k = j + 1 + kk;
-      sa[k * ld + i] -= sa[j * ld + i] * sa[k * ld + j];
+    if (r > 0) {
+      const int dk = LB / r, di = LB - dk * r;
+      int kk = tid / r, ii = tid - kk * r;
+      for (int e = tid; e < r * r; e += LB) {
+        const int i = j + 1 + ii, k = j + 1 + kk;
+        sa[k * ld + i] -= sa[j * ld + i] * sa[k * ld + j];
+        ii += di;
+        kk += dk;
+        if (ii >= r) {
+          ii -= r;
+          ++kk;
+        }
+      }
     }
     __syncthreads();
   }
@@ -1020,9 +1030,19 @@ __global__ __launch_bounds__(LB) void lu_blocked_kernel(double* mats, double* rh
       __syncthreads();
       // rest of the panel: columns c + 1 .. nb - 1
       const int r = m - j - 1;
-      for (int e = tid; e < r * (nb - c - 1); e += LB) {
-        const int cc = c + 1 + e / r, i = j + 1 + e % r;
-        pan[cc * m + i] -= pan[c * m + i] * pan[cc * m + j];
+      if (r > 0) {
+        const int dk = LB / r, di = LB - dk * r;
+        int kk = tid / r, ii = tid - kk * r;
+        for (int e = tid; e < r * (nb - c - 1); e += LB) {
+          const int cc = c + 1 + kk, i = j + 1 + ii;
+          pan[cc * m + i] -= pan[c * m + i] * pan[cc * m + j];
+          ii += di;
+          kk += dk;
+          if (ii >= r) {
+            ii -= r;
+            ++kk;
+          }
+        }
       }
       __syncthreads();
     }
@@ -1058,12 +1078,23 @@ __global__ __launch_bounds__(LB) void lu_blocked_kernel(double* mats, double* rh
       }
       __syncthreads();
       // 6. trailing update A22 -= L21 U12
+      // (linear index e = kk r + ii stepped without a division per element)
       const int r = m - k1, w = m - k1;
-      for (long e = tid; e < (long)r * w; e += LB) {
-        const int kk = (int)(e / r), i = k1 + (int)(e % r), k = k1 + kk;
+      const int dk = LB / r, di = LB - dk * r;
+      int kk = tid / r, ii = tid - kk * r;
+      for (int e = tid; e < r * w; e += LB) {
+        const int i = k1 + ii, k = k1 + kk;
         double t = a[(long)k * m + i];
-        for (int c = 0; c < nb; ++c) t -= pan[c * m + i] * u12[c * m + k];
+        // a trailing block exists only below a full panel (nb == NBK)
+#pragma unroll
+        for (int c = 0; c < NBK; ++c) t -= pan[c * m + i] * u12[c * m + k];
         a[(long)k * m + i] = t;
+        ii += di;
+        kk += dk;
+        if (ii >= r) {
+          ii -= r;
+          ++kk;
+        }
       }
     }
     __syncthreads();

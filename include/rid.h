@@ -176,7 +176,7 @@ typedef struct {
   int32_t n_inner_iter;  /* inner block products */
   int32_t n_history;
   double history[RID_MAX_HISTORY]; /* max residual norm per outer iteration */
-  double t_matvec_ms;    /* outer operator products */
+  double t_matvec_ms;    /* outer operator products (device time; submission time when sharing a batch) */
   double t_precond_ms;   /* preconditioner and ris initial guess */
   double t_other_ms;     /* projection, small dense, residuals, orthonormalisation */
   double t_total_ms;

@@ -54,16 +54,47 @@ struct Eng {
   Batcher* batcher;
   OpWork own;     // operator scratch of a solve that shares the device
   hipEvent_t ready = nullptr;
+  // timing of the outer products: event pairs read once the solve has
+  // synchronised anyway, so that no product waits for the host
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> mv_ev;
   Eng(rid_problem* p, SolveStats* s, const ExecCfg& ex)
       : fence(ex.stream ? ex.stream : p->ctx->stream), P(p), st(ex.stream ? ex.stream : p->ctx->stream), N(p->n()), part(p->ctx), tmp1(p->ctx), tmp2(p->ctx),
         ints(p->ctx), dscal(p->ctx), stats(s), batcher(ex.batcher), own(p->ctx) {
     if (batcher) RID_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
   }
   ~Eng() {
-    if (ready) {
-      (void)hipStreamSynchronize(st);
-      (void)hipEventDestroy(ready);
+    if (ready || !ev_pool.empty() || !mv_ev.empty()) (void)hipStreamSynchronize(st);
+    if (ready) (void)hipEventDestroy(ready);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (auto& pr : mv_ev) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
     }
+  }
+  hipEvent_t get_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    RID_HIP(hipEventCreate(&e));
+    return e;
+  }
+  // Device time of the outer products recorded so far (ms); waits for them.
+  double take_product_ms() {
+    double t = 0.0;
+    for (auto& pr : mv_ev) {
+      RID_HIP(hipEventSynchronize(pr.second));
+      float ms = 0.0f;
+      RID_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      t += ms;
+      ev_pool.push_back(pr.first);
+      ev_pool.push_back(pr.second);
+    }
+    mv_ev.clear();
+    return t;
   }
   Eng(const Eng&) = delete;
   Eng& operator=(const Eng&) = delete;
@@ -281,15 +312,28 @@ int append_orthonormal(Eng& E, Basis& B, double* W, int nnew, double drop_tol = 
 }
 
 // Products of the new basis vectors [m0, m) with the operator.
-void multiply(Eng& E, Basis& B, int m0, int kind, int prec, double& t_acc) {
+// t_acc: null for products that are not timed (the inner ones).  A solve
+// alone on its stream brackets the product with events (read later by
+// take_product_ms, no wait here); one that shares the device counts the
+// submission time.
+void multiply(Eng& E, Basis& B, int m0, int kind, int prec, double* t_acc) {
   const int nn = B.m - m0;
   if (nn <= 0) return;
-  auto t0 = Clock::now();
+  if (!t_acc) {
+    E.apply(kind, prec, nn, B.V(m0), B.P1(m0), B.nprod == 2 ? B.P2(m0) : nullptr);
+    return;
+  }
+  if (E.batcher) {
+    auto t0 = Clock::now();
+    E.apply(kind, prec, nn, B.V(m0), B.P1(m0), B.nprod == 2 ? B.P2(m0) : nullptr);
+    *t_acc += ms_since(t0);
+    return;
+  }
+  hipEvent_t a = E.get_event(), b = E.get_event();
+  RID_HIP(hipEventRecord(a, E.st));
   E.apply(kind, prec, nn, B.V(m0), B.P1(m0), B.nprod == 2 ? B.P2(m0) : nullptr);
-  // alone, wait for the product so that its time is known; a solve that
-  // shares the device goes on enqueueing (its time then counts submission)
-  if (!E.batcher) E.sync();
-  t_acc += ms_since(t0);
+  RID_HIP(hipEventRecord(b, E.st));
+  E.mv_ev.emplace_back(a, b);
 }
 
 // Update the projected matrices with the columns [m0, m).
@@ -453,8 +497,7 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
   diag_tda(E.P->de.as<double>(), rh.as<double>(), N, nr, N, sh, nullptr, wn.as<double>(), N, E.st);
   append_orthonormal(E, U, wn.as<double>(), nr);
   const int kind = OPK_T;
-  double tdummy = 0.0;
-  multiply(E, U, 0, kind, prec, tdummy);
+  multiply(E, U, 0, kind, prec, nullptr);
   project(E, U, 0);
   res.n_mv = U.m;
   res.n_iter = 1;
@@ -501,7 +544,7 @@ InnerResult inner_single(Eng& E, int prec, const double* r, int nr, const std::v
     const int m0 = U.m;
     const int added = append_orthonormal(E, U, wn.as<double>(), (int)act.size());
     if (added == 0) break;
-    multiply(E, U, m0, kind, prec, tdummy);
+    multiply(E, U, m0, kind, prec, nullptr);
     project(E, U, m0);
     res.n_mv += added;
     res.n_iter += 1;
@@ -609,8 +652,7 @@ InnerResult inner_pair(Eng& E, int prec, const double* r1, const double* r2, int
             wn.as<double>() + (long)nr * N, N, E.st);
   append_orthonormal(E, U, wn.as<double>(), 2 * nr);
   const int kind = OPK_TPAIR;
-  double tdummy = 0.0;
-  multiply(E, U, 0, kind, prec, tdummy);
+  multiply(E, U, 0, kind, prec, nullptr);
   project(E, U, 0);
   res.n_mv = U.m;
   res.n_iter = 1;
@@ -665,7 +707,7 @@ InnerResult inner_pair(Eng& E, int prec, const double* r1, const double* r2, int
     const int m0 = U.m;
     const int added = append_orthonormal(E, U, wn.as<double>(), 2 * na);
     if (added == 0) break;
-    multiply(E, U, m0, kind, prec, tdummy);
+    multiply(E, U, m0, kind, prec, nullptr);
     project(E, U, m0);
     res.n_mv += added;
     res.n_iter += 1;
@@ -710,7 +752,7 @@ void davidson_sym(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
   RID_HIP(hipMemcpyAsync(wn.p, v0, sizeof(double) * n0 * N, hipMemcpyDeviceToDevice, E.st));
   append_orthonormal(E, B, wn.as<double>(), n0);
   RID_CHECK(B.m > 0, RID_ERR_BREAKDOWN, "initial subspace is empty");
-  multiply(E, B, 0, kind, prec, tmv);
+  multiply(E, B, 0, kind, prec, &tmv);
   project(E, B, 0);
   core.n_iter = 1;
   core.n_mv = B.m;
@@ -779,7 +821,7 @@ void davidson_sym(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
       core.status = RID_ERR_BREAKDOWN;
       break;
     }
-    multiply(E, B, m0, kind, prec, tmv);
+    multiply(E, B, m0, kind, prec, &tmv);
     t0 = Clock::now();
     project(E, B, m0);
     if (timed) st.t_other += ms_since(t0);
@@ -787,6 +829,7 @@ void davidson_sym(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
     core.n_mv += added;
     E.track(B.bytes() + E.P->footprint());
   }
+  tmv += E.take_product_ms();
   if (timed) st.t_matvec += tmv;
   (void)t_start;
 }
@@ -886,7 +929,7 @@ void davidson_rpa(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
   RID_HIP(hipMemcpyAsync(wn.p, v0, sizeof(double) * n0 * N, hipMemcpyDeviceToDevice, E.st));
   append_orthonormal(E, B, wn.as<double>(), n0);
   RID_CHECK(B.m > 0, RID_ERR_BREAKDOWN, "initial subspace is empty");
-  multiply(E, B, 0, kind, prec, tmv);
+  multiply(E, B, 0, kind, prec, &tmv);
   project(E, B, 0);
   core.n_iter = 1;
   core.n_mv = B.m;
@@ -956,7 +999,7 @@ void davidson_rpa(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
       core.status = RID_ERR_BREAKDOWN;
       break;
     }
-    multiply(E, B, m0, kind, prec, tmv);
+    multiply(E, B, m0, kind, prec, &tmv);
     t0 = Clock::now();
     project(E, B, m0);
     if (timed) st.t_other += ms_since(t0);
@@ -964,6 +1007,7 @@ void davidson_rpa(Eng& E, int kind, int prec, int k, const double* v0, int n0, c
     core.n_mv += added;
     E.track(B.bytes() + E.P->footprint());
   }
+  tmv += E.take_product_ms();
   if (timed) st.t_matvec += tmv;
 }
 
@@ -1230,7 +1274,7 @@ rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, con
   append_orthonormal(E, B, u0.as<double>(), 2 * npair);
   RID_CHECK(B.m > 0, RID_ERR_BREAKDOWN, "initial subspace is empty");
   double tmv = 0.0;
-  multiply(E, B, 0, OPK_PAIR, pout, tmv);
+  multiply(E, B, 0, OPK_PAIR, pout, &tmv);
   project(E, B, 0);
   st.n_iter = 1;
   st.n_mv = B.m;
@@ -1317,7 +1361,7 @@ rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, con
     const int added = append_orthonormal(E, B, wn.as<double>(), 2 * na);
     st.t_other += ms_since(t0);
     if (added == 0) throw Error(RID_ERR_BREAKDOWN, "every new direction was dropped");
-    multiply(E, B, m0, OPK_PAIR, pout, tmv);
+    multiply(E, B, m0, OPK_PAIR, pout, &tmv);
     t0 = Clock::now();
     project(E, B, m0);
     st.t_other += ms_since(t0);
@@ -1325,6 +1369,7 @@ rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, con
     st.n_mv += added;
     E.track(B.bytes() + P->footprint());
   }
+  tmv += E.take_product_ms();
   st.t_matvec += tmv;
   // alpha[f][u][v] = -2 P_u^T U_{v,f} = 2 (-P_u)^T U_{v,f}
   DevBuf al(ctx);

@@ -144,10 +144,11 @@ __global__ __launch_bounds__(DB) void jacobi_kernel(double* a, int m, int lda, d
 }
 
 // k lowest eigenpairs of a symmetric matrix: Householder reduction to
-// tridiagonal form T = H^T a H (H = H_0 ... H_{m-3}), Sturm-count bisection
-// for the eigenvalues of T, inverse iteration with partial pivoting for its
-// eigenvectors (re-orthogonalised within clusters of close eigenvalues at
-// every iteration), and back-transformation by the reflectors.
+// tridiagonal form T = H^T a H (H = H_0 ... H_{m-3}), Sturm-count
+// multisection (bisection with 64 points per step) for the eigenvalues of T,
+// inverse iteration with partial pivoting for its eigenvectors
+// (re-orthogonalised within clusters of close eigenvalues at every
+// iteration), and back-transformation by the reflectors.
 // work: 3 m + 6 m k + 2 m doubles.
 __device__ inline int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int m, double x,
                                   double pivmin) {

@@ -73,7 +73,8 @@ size_t small_syevx_work(int m, int k);
 void small_syevx(double* a, int m, int lda, int k, double* w, double* q, int ldq, double* work, hipStream_t s);
 // Cholesky a = L L^T in place (lower triangle, upper zeroed); info[0] = 0 on
 // success, j+1 if the j-th pivot is not positive (that pivot is replaced by
-// 1 and the factorisation goes on).  One wavefront for m <= 64.
+// 1 and the factorisation goes on).  One wavefront for m <= 64, panels of
+// 16 columns in LDS for m <= 512, column by column beyond.
 void small_chol(double* a, int m, int lda, int* info, hipStream_t s);
 // Batched dense solve with partial pivoting: for b < nb, solve
 // M_b y_b = g_b where M_b is m x m at mats + b * m * m (row-major; destroyed)

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 from oracle import operators as ops
-from synth import config_sizes, make_block, make_problem
+from synth import config_sizes, make_block, make_dipoles, make_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -91,3 +91,28 @@ def test_c2_mixed_rpa_roots_are_oracle_eigenpairs(c2):
     assert worst < 1e-5
     # roots are positive, ascending, below the smallest orbital-energy gap plus coupling
     assert np.all(np.diff(om) >= 0) and om[0] > 0
+
+
+def test_c2_mixed_static_polarizability_residual_entries(c2):
+    """The static response solve bench.py times (3 dipole right-hand sides,
+    w = 0, rid preconditioner, mixed precision): (A+B) U = -P (Eq.
+    TDDFT_polar at w = 0) checked on sampled entries by the oracle, and
+    alpha = -2 P^T U, symmetric."""
+    p, ctx, prob, host = c2
+    pd = make_dipoles(p, 3)
+    out = prob.polarizability(pd, [0.0], "ris", "mixed", vectors=True)
+    assert out["status"] == 0
+    assert np.all(out["resid"] < 1e-5)
+    u = out["u"].cpu().numpy()[0]
+    pn = pd.cpu().numpy()
+    alpha = out["alpha"][0]
+    np.testing.assert_allclose(alpha, -2.0 * pn @ u.T, rtol=1e-10, atol=1e-12 * np.abs(alpha).max())
+    # symmetric up to the solve tolerance (each U_v has relative residual < 1e-5)
+    np.testing.assert_allclose(alpha, alpha.T, rtol=0, atol=1e-4 * np.abs(alpha).max())
+    worst = 0.0
+    for v in range(3):
+        apb_u = _oracle_entries(p, host, u[v].reshape(p.no, p.nv), SAMPLES)[:, 0]
+        rhs = np.array([pn[v, i * p.nv + a] for i, a in SAMPLES])
+        worst = max(worst, np.abs(apb_u + rhs).max() / np.linalg.norm(pn[v]))
+    print("largest sampled relative residual entry:", worst, flush=True)
+    assert worst < 1e-5

@@ -329,11 +329,23 @@ void multiply(Eng& E, Basis& B, int m0, int kind, int prec, double* t_acc) {
     *t_acc += ms_since(t0);
     return;
   }
-  hipEvent_t a = E.get_event(), b = E.get_event();
-  RID_HIP(hipEventRecord(a, E.st));
+  // the pair goes back to the pool if the product throws
+  struct Pair {
+    Eng& E;
+    hipEvent_t a, b;
+    bool used = false;
+    ~Pair() {
+      if (!used) {
+        E.ev_pool.push_back(a);
+        E.ev_pool.push_back(b);
+      }
+    }
+  } pr{E, E.get_event(), E.get_event()};
+  RID_HIP(hipEventRecord(pr.a, E.st));
   E.apply(kind, prec, nn, B.V(m0), B.P1(m0), B.nprod == 2 ? B.P2(m0) : nullptr);
-  RID_HIP(hipEventRecord(b, E.st));
-  E.mv_ev.emplace_back(a, b);
+  RID_HIP(hipEventRecord(pr.b, E.st));
+  E.mv_ev.emplace_back(pr.a, pr.b);
+  pr.used = true;
 }
 
 // Update the projected matrices with the columns [m0, m).

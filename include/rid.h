@@ -101,9 +101,11 @@ typedef struct rid_context rid_context;
 typedef struct rid_problem rid_problem;
 typedef struct rid_server rid_server;
 
-/* Device memory provider.  alloc returns a device pointer with at least
- * 256-byte alignment or NULL; free releases it.  Both are called from the
- * thread that calls into the library (or the server's worker thread). */
+/* Device memory provider (required by rid_context_create).  alloc returns a
+ * device pointer with at least 256-byte alignment or NULL; free releases it.
+ * Either may be called from any thread of the library -- the caller's, the
+ * solve threads of rid_batch_solve and of the server, and their product
+ * threads -- but never two at once: the library serialises the calls. */
 typedef struct {
   void* user;
   void* (*alloc)(void* user, size_t bytes);
@@ -193,7 +195,9 @@ RID_API const char* rid_last_error(const rid_context* ctx);
 
 /* ---- context ----------------------------------------------------------
  * device: HIP device ordinal; hip_stream: a hipStream_t (NULL = the null
- * stream); alloc: NULL = the library's own hipMalloc/hipFree. */
+ * stream); alloc: required -- every device buffer the library uses comes
+ * from alloc->alloc and goes back through alloc->free (the library never
+ * calls hipMalloc); NULL, or a NULL callback, gives RID_ERR_INVALID_ARG. */
 RID_API rid_status rid_context_create(int32_t device, void* hip_stream, const rid_allocator* alloc,
                               rid_context** out);
 RID_API rid_status rid_context_destroy(rid_context* ctx);

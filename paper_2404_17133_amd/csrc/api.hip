@@ -93,6 +93,9 @@ rid_status rid_context_create(int32_t device, void* hip_stream, const rid_alloca
   return guarded(nullptr, [&]() -> rid_status {
     RID_CHECK(out != nullptr, RID_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    RID_CHECK(alloc && alloc->alloc && alloc->free, RID_ERR_INVALID_ARG,
+              "an allocator with alloc and free callbacks is required (the library allocates device memory only "
+              "through it)");
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
       (void)hipGetLastError();
@@ -103,14 +106,10 @@ rid_status rid_context_create(int32_t device, void* hip_stream, const rid_alloca
     RID_HIP(hipGetDeviceProperties(&prop, device));
     RID_CHECK(std::strncmp(prop.gcnArchName, "gfx950", 6) == 0, RID_ERR_NO_DEVICE,
               std::string("library built for gfx950, device is ") + prop.gcnArchName);
-    if (alloc) RID_CHECK(alloc->alloc && alloc->free, RID_ERR_INVALID_ARG, "allocator callbacks missing");
     rid_context* c = new rid_context();
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    if (alloc) {
-      c->alloc = *alloc;
-      c->user_alloc = true;
-    }
+    c->alloc = *alloc;
     *out = c;
     return RID_OK;
   });

@@ -94,29 +94,16 @@ ProfScope::~ProfScope() {
 
 void* dev_alloc(rid_context* ctx, size_t bytes) {
   if (bytes == 0) bytes = 256;
-  void* p = nullptr;
-  if (ctx->user_alloc) {
-    std::lock_guard<std::mutex> g(ctx->mu);
-    p = ctx->alloc.alloc(ctx->alloc.user, bytes);
-    RID_CHECK(p != nullptr, RID_ERR_NO_MEMORY, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
-  } else {
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error(RID_ERR_NO_MEMORY, "hipMalloc(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
-    }
-  }
+  std::lock_guard<std::mutex> g(ctx->mu);
+  void* p = ctx->alloc.alloc(ctx->alloc.user, bytes);
+  RID_CHECK(p != nullptr, RID_ERR_NO_MEMORY, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
   return p;
 }
 
 void dev_free(rid_context* ctx, void* p) {
   if (!p) return;
-  if (ctx->user_alloc) {
-    std::lock_guard<std::mutex> g(ctx->mu);
-    ctx->alloc.free(ctx->alloc.user, p);
-  } else {
-    (void)hipFree(p);
-  }
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->alloc.free(ctx->alloc.user, p);
 }
 
 namespace {

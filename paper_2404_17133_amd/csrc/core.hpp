@@ -64,8 +64,7 @@ class Batcher;
 struct rid_context {
   int device = 0;
   hipStream_t stream = nullptr;
-  rid_allocator alloc{};
-  bool user_alloc = false;
+  rid_allocator alloc{};  // every device buffer of the library comes from here
   std::string last_error;
   std::mutex mu;  // guards allocator use from several host threads
   rid::Profiler prof;

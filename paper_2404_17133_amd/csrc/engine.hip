@@ -453,7 +453,8 @@ void ritz_rpa(Eng& E, Ritz& R, Basis& B, int k, std::vector<double>& w2_host, in
   double* om = R.om.as<double>();
   double* f1 = om + kk;
   double* f2 = om + 2 * kk;
-  hipLaunchKernelGGL(rpa_scale_kernel, dim3(1), dim3(256), 0, E.st, R.w.as<double>(), kk, om, f1, f2);
+  hipLaunchKernelGGL(rpa_scale_kernel, dim3(ceil_div(kk, 256)), dim3(256), 0, E.st, R.w.as<double>(), kk, om, f1,
+                     f2);
   // z = L q[:, :k] / sqrt(Omega), z' = a_+ z / Omega
   small_gemm(0, 0, m, kk, m, 1.0, R.lmat.as<double>(), m, R.q.as<double>(), kk, 0.0, R.zc.as<double>(), kk, E.st);
   hipLaunchKernelGGL(scale_small_cols_kernel, dim3(ceil_div(m * kk, 256)), dim3(256), 0, E.st, R.zc.as<double>(), m,
@@ -1060,7 +1061,16 @@ rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode,
   const bool ris = o.precond == RID_PRECOND_RIS;
   const int extra = o.n_extra_init >= 0 ? o.n_extra_init : (ris ? std::min(k, 3) : 8);
   const int n_init = (int)std::min<long>(N, k + extra);
-  const int m_max = std::max(default_m_max(k, o.m_max), 2 * n_init + 4 * k + 8);
+  // the subspace must hold a restart (N_init vectors) plus two blocks of new
+  // directions, and stay within the projected-problem limit of the dense
+  // eigensolver: both checked before any work
+  const int m_floor = 2 * n_init + 4 * k + 8;
+  RID_CHECK(m_floor <= kMaxProjected, RID_ERR_SHAPE,
+            "k = " + std::to_string(k) + " needs a subspace of at least " + std::to_string(m_floor) +
+                " vectors, above the projected-problem limit of " + std::to_string(kMaxProjected));
+  const int m_max = std::min(kMaxProjected, std::max(default_m_max(k, o.m_max), m_floor));
+  RID_CHECK(o.n_guess + n_init <= kMaxProjected, RID_ERR_SHAPE,
+            "warm-start vectors plus N_init exceed the projected-problem limit of " + std::to_string(kMaxProjected));
   const int pin = ris_prec(o), pout = outer_prec(o);
   const double* de = P->de.as<double>();
   DevBuf v0(ctx), zbuf(ctx), zpbuf(ctx), posd(ctx);
@@ -1101,7 +1111,7 @@ rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode,
         return (int)act.size();
       };
       davidson_sym(E, OPK_T, pin, n_init, u.as<double>(), nt, dpc, o.init_tol, o.init_max_iter,
-                   std::max(200, 40 * n_init), n_init, v0.as<double>(), g, false);
+                   std::min(kMaxProjected, std::max(200, 40 * n_init)), n_init, v0.as<double>(), g, false);
       st.n_inner_mv += g.n_mv;
       st.n_inner_iter += g.n_iter;
     }
@@ -1130,7 +1140,7 @@ rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode,
         return 2 * na;
       };
       davidson_rpa(E, OPK_TPAIR, pin, n_init, u.as<double>(), nt, dpc, o.init_tol, o.init_max_iter,
-                   std::max(200, 40 * n_init), n_init, v0.as<double>(), v0.as<double>() + (long)n_init * N, g,
+                   std::min(kMaxProjected, std::max(200, 40 * n_init)), n_init, v0.as<double>(), v0.as<double>() + (long)n_init * N, g,
                    false);
       st.n_inner_mv += g.n_mv;
       st.n_inner_iter += g.n_iter;

@@ -68,7 +68,8 @@ void chol_check_pack(const double* l, int n, int ldl, const double* nrm, const i
 void small_eigh(double* a, int m, int lda, double* w, double* q, double* work, hipStream_t s);
 // The k lowest eigenpairs of symmetric a (m x m, lda; destroyed): w[k]
 // ascending, q[i * ldq + t] = component i of eigenvector t.  work >=
-// small_syevx_work(m, k) doubles.
+// small_syevx_work(m, k) doubles.  m is at most kMaxProjected.
+constexpr int kMaxProjected = 1024;  // largest projected dimension of the dense eigen/Cholesky kernels
 size_t small_syevx_work(int m, int k);
 void small_syevx(double* a, int m, int lda, int k, double* w, double* q, int ldq, double* work, hipStream_t s);
 // Cholesky a = L L^T in place (lower triangle, upper zeroed); info[0] = 0 on

@@ -13,6 +13,7 @@
 // step s consumes the s-th element(s) of every group's slice.  Since A and B
 // use the same permutation the sum over K is unchanged.
 #include "gemm.hpp"
+#include "gemm_limits.hpp"
 
 #include <algorithm>
 
@@ -476,7 +477,8 @@ bool vec_ok(const GemmParams& p) {
   const int vw = 16 / elem_size<T>();
   return (p.K % vw == 0) && (p.lda % vw == 0) && (p.ldb % vw == 0) && (p.sAp % vw == 0) && (p.sBp % vw == 0) &&
          (p.sA1 % vw == 0) && (p.sA2 % vw == 0) && (p.sB1 % vw == 0) && (p.sB2 % vw == 0) &&
-         ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.B % 16 == 0);
+         ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.B % 16 == 0) &&
+         gemm_offsets_fit(p.lda, p.ldb, p.K, elem_size<T>());
 }
 
 void check_params(const GemmParams& p, int nz, int nsplit) {

@@ -48,37 +48,34 @@ def _need_dev(t: torch.Tensor, shape, name, dtypes=(torch.float64,)):
 class Context:
     """A device, a stream and a PyTorch-backed device allocator."""
 
-    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None):
         self.device = device
         self.stream = stream or torch.cuda.current_stream(device)
         self._children = weakref.WeakSet()  # problems and servers, closed before the context
         blocks = {}
         self._blocks = blocks
-        self._alloc_ref = None
-        alloc = None
-        if torch_allocator:
-            dev = torch.device("cuda", device)
+        dev = torch.device("cuda", device)
 
-            # the callbacks hold the block table, not the context, so that no
-            # reference cycle decides the order of finalisation
-            def _alloc(user, nbytes):
-                try:
-                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
-                except Exception as e:  # out of memory: the library reports RID_ERR_NO_MEMORY
-                    blocks["last_failure"] = "%d bytes: %s" % (int(nbytes), str(e).splitlines()[0][:300])
-                    return None
-                blocks[t.data_ptr()] = t
-                return t.data_ptr()
+        # the callbacks hold the block table, not the context, so that no
+        # reference cycle decides the order of finalisation
+        def _alloc(user, nbytes):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+            except Exception as e:  # out of memory: the library reports RID_ERR_NO_MEMORY
+                blocks["last_failure"] = "%d bytes: %s" % (int(nbytes), str(e).splitlines()[0][:300])
+                return None
+            blocks[t.data_ptr()] = t
+            return t.data_ptr()
 
-            def _free(user, p):
-                if p:
-                    blocks.pop(int(p), None)
+        def _free(user, p):
+            if p:
+                blocks.pop(int(p), None)
 
-            self._alloc_ref = (B.ALLOC_FN(_alloc), B.FREE_FN(_free))
-            alloc = B.rid_allocator(None, self._alloc_ref[0], self._alloc_ref[1])
+        self._alloc_ref = (B.ALLOC_FN(_alloc), B.FREE_FN(_free))
+        alloc = B.rid_allocator(None, self._alloc_ref[0], self._alloc_ref[1])
         h = ctypes.c_void_p()
         s = B.lib.rid_context_create(device, ctypes.c_void_p(self.stream.cuda_stream),
-                                     ctypes.byref(alloc) if alloc is not None else None, ctypes.byref(h))
+                                     ctypes.byref(alloc), ctypes.byref(h))
         if s != B.RID_OK:
             raise RidError(s, B.lib.rid_last_error(None).decode())
         self.handle = h

@@ -59,6 +59,27 @@ def test_null_arguments_rejected_without_device():
     assert L.rid_server_poll(None, 1) == B.RID_ERR_INVALID_ARG
 
 
+def _dummy_allocator(B):
+    fns = (B.ALLOC_FN(lambda user, n: None), B.FREE_FN(lambda user, p: None))
+    return fns, B.rid_allocator(None, fns[0], fns[1])
+
+
+def test_context_needs_an_allocator():
+    """The library allocates device memory only through the caller's
+    allocator: a missing allocator or callback is refused before any device
+    is touched."""
+    from paper_2404_17133_amd import _binding as B
+
+    h = ctypes.c_void_p()
+    assert B.lib.rid_context_create(0, None, None, ctypes.byref(h)) == B.RID_ERR_INVALID_ARG
+    assert h.value is None
+    assert b"allocator" in B.lib.rid_last_error(None)
+    keep, al = _dummy_allocator(B)
+    half = B.rid_allocator(None, keep[0], B.FREE_FN())
+    assert B.lib.rid_context_create(0, None, ctypes.byref(half), ctypes.byref(h)) == B.RID_ERR_INVALID_ARG
+    assert h.value is None
+
+
 def test_context_without_gpu_reports_no_device():
     import torch
 
@@ -66,8 +87,9 @@ def test_context_without_gpu_reports_no_device():
         pytest.skip("a GPU is visible")
     from paper_2404_17133_amd import _binding as B
 
+    keep, al = _dummy_allocator(B)
     h = ctypes.c_void_p()
-    s = B.lib.rid_context_create(0, None, None, ctypes.byref(h))
+    s = B.lib.rid_context_create(0, None, ctypes.byref(al), ctypes.byref(h))
     assert s == B.RID_ERR_NO_DEVICE
     assert h.value is None
     assert len(B.lib.rid_last_error(None)) > 0

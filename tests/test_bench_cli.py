@@ -16,14 +16,25 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.stdout == ""
 
 
-def test_traffic_lookup_matches_the_committed_counter_summary():
-    sys.path.insert(0, ROOT)
-    import bench
+def test_traffic_lookup_matches_the_committed_counter_summary(monkeypatch):
+    import re
 
+    sys.path.insert(0, ROOT)
+    sys.path.insert(0, os.path.join(ROOT, "paper_2404_17133_amd"))
+    import bench
+    import profsum
+
+    text = open(os.path.join(ROOT, "profiles", "exch_contractions_c2_mixed_hbm_traffic.md")).read()
+    taken = re.search(r"GEMM source hash: (\w+)", text).group(1)
+    # with the GEMM source the counters were taken with, the summary's
+    # dispatch-weighted bytes per launch are reported
+    monkeypatch.setattr(profsum, "gemm_source_hash", lambda: taken)
     t = bench.measured_traffic("exch_w", "f32", "c2")
-    # the committed summary was taken with the GEMM source as it stands
     assert t is not None and t > 0
-    # about 1.7 GB per launch against 0.37 GB of algorithmic bytes
-    assert 1e9 < t < 3e9
+    # more than the 0.37 GB of algorithmic bytes per launch, less than 3 GB
+    assert 0.37e9 < t < 3e9
     assert bench.measured_traffic("exch_w", "f32", "c1") is None  # only the no=200 workload was counted
     assert bench.measured_traffic("no_such_family", "f32", "c2") is None
+    # once the GEMM source changes, the old counters no longer describe it
+    monkeypatch.setattr(profsum, "gemm_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic("exch_w", "f32", "c2") is None

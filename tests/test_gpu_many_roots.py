@@ -57,3 +57,58 @@ def test_forty_roots_match_exact_spectrum(mode):
     assert err < 1e-8, err
     assert np.all(out["resid"] < 1e-9)
     ctx.close()
+
+
+_CACHE30 = {}
+
+
+def exact_c0():
+    """The no=20, nv=80 problem (N = 1600) and its exact 30 lowest roots."""
+    if "p" not in _CACHE30:
+        p = make_problem(20, 80, 400, 90, seed=0)
+        op = OracleProblem.from_arrays(p.numpy())
+        eye = np.eye(p.n)
+        a = apply_a(op, eye)
+        apb, amb = apply_apb_amb(op, eye)
+        a, apb, amb = (0.5 * (m + m.T) for m in (a, apb, amb))
+        ev, u = np.linalg.eigh(amb)
+        s = (u * np.sqrt(ev)) @ u.T
+        _CACHE30["p"] = (p, {"tda": np.linalg.eigvalsh(a)[:30],
+                             "rpa": np.sqrt(np.linalg.eigvalsh(s @ apb @ s)[:30])})
+    return _CACHE30["p"]
+
+
+@pytest.mark.parametrize("mode", ["tda", "rpa"])
+def test_thirty_roots_with_the_subspace_at_its_cap(mode):
+    """k = 30 on N = 1600: the default cap max(200, 40 k) = 1200 is above the
+    projected-problem limit of the dense eigensolver (1024), so the subspace
+    is capped at 1024 and restarts there; the roots still match the exact
+    spectrum."""
+    import paper_2404_17133_amd as rid
+
+    p, ref = exact_c0()
+    ctx = rid.Context(0)
+    prob = rid.Problem.from_synth(ctx, p.to("cuda:0"))
+    print("thirty roots", mode, "N", p.n, flush=True)
+    out = prob.eigen(30, mode, "diag", "fp64", tol=1e-9)
+    assert out["status"] == 0
+    err = np.abs(out["omega"] - ref[mode]).max()
+    print("max |dOmega|", err, "n_mv", out["stats"]["n_mv"], "iters", out["stats"]["n_iter"], flush=True)
+    assert err < 1e-8, err
+    ctx.close()
+
+
+def test_too_many_roots_rejected_before_any_work():
+    """k whose minimum subspace (2 N_init + 4 k + 8) exceeds the projected
+    limit is refused with RID_ERR_SHAPE up front."""
+    import paper_2404_17133_amd as rid
+    from paper_2404_17133_amd import _binding as B
+
+    p, _ = exact_c0()
+    ctx = rid.Context(0)
+    prob = rid.Problem.from_synth(ctx, p.to("cuda:0"))
+    with pytest.raises(rid.RidError) as e:
+        prob.eigen(200, "tda", "diag", "fp64")
+    assert e.value.status == B.RID_ERR_SHAPE
+    assert "projected-problem limit" in str(e.value)
+    ctx.close()

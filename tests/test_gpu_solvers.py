@@ -62,6 +62,7 @@ def test_tda_config0(precond, precision):
 def test_rpa_config0(precond, precision):
     p, op = config0()
     ref = eigen_rpa(op, 5, "diag", tol=1e-8)
+    ref5 = eigen_rpa(op, 5, precond, tol=1e-5)
     ctx, prob = gpu_problem(p)
     print("rpa", precond, precision, flush=True)
     out = prob.eigen(5, "rpa", precond, precision)
@@ -70,6 +71,11 @@ def test_rpa_config0(precond, precision):
     assert err < 1e-6, err
     x, y = out["x"].cpu().numpy(), out["y"].cpu().numpy()
     np.testing.assert_allclose(np.sum(x * x, axis=1) - np.sum(y * y, axis=1), 1.0, atol=1e-8)
+    # the preconditioner decides the iteration count (the paper's figure of
+    # merit): the FP64 path follows the oracle's count (same algorithm, up to
+    # rounding that may move one residual across the threshold)
+    if precision == "fp64":
+        assert abs(out["stats"]["n_iter"] - ref5.n_iter) <= 1, (out["stats"]["n_iter"], ref5.n_iter)
     ctx.close()
 
 
@@ -80,12 +86,15 @@ def test_polarizability_config0(precond, precision):
     pm = make_dipoles(p, 3)
     om = [0.0, 0.0569542, 0.2]
     ref = polarizability(op, pm.numpy().T, om, "diag", tol=1e-8)
+    ref5 = polarizability(op, pm.numpy().T, om, precond, tol=1e-5)
     ctx, prob = gpu_problem(p)
     print("alpha", precond, precision, flush=True)
     out = prob.polarizability(pm.to("cuda:0").contiguous(), om, precond, precision)
     assert out["status"] == 0
     rel = np.abs(out["alpha"] - ref.alpha).max() / np.abs(ref.alpha).max()
     assert rel < 1e-5, rel
+    if precision == "fp64":
+        assert abs(out["stats"]["n_iter"] - ref5.n_iter) <= 1, (out["stats"]["n_iter"], ref5.n_iter)
     ctx.close()
 
 

@@ -225,6 +225,39 @@ RID_API void rid_solve_opts_default(rid_solve_opts* opts);
 RID_API rid_status rid_apply_operator(rid_problem* prob, int32_t op, int32_t precision, int32_t nvec,
                               const double* x_dev, double* y_dev, double* y2_dev);
 
+/* ---- operator products without allocation ------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * operation, arguments and layouts as rid_apply_operator, but:
+ *   - every intermediate of the product (vector layouts in the compute type,
+ *     Coulomb partial sums, exchange chunks S^P / Q^P, split partial sums)
+ *     lives in one fixed device region of RID_NOALLOC_SCRATCH_BYTES per GPU,
+ *     a static array of the library whose device address is looked up once
+ *     per device by rid_context_create; the region is held until the
+ *     process ends;
+ *   - no allocator call, hipMalloc/hipFree, event creation or autotuning
+ *     run (the tile shape follows the untuned default rule, at most 16
+ *     partial sums per reduction, exchange chunks of at most one eighth of
+ *     the region), and no profiling events are recorded; results agree with
+ *     rid_apply_operator up to the rounding of the partial sums;
+ *   - the problem's tensor copies for this operator and precision must exist
+ *     already: a first rid_apply_operator or solve in that precision makes
+ *     them (RID_ERR_INVALID_ARG otherwise);
+ *   - a product whose intermediates do not fit the region returns
+ *     RID_ERR_SHAPE before any kernel runs (roughly: nvec * N * 40 bytes of
+ *     vector layouts plus the Coulomb and exchange partials must stay under
+ *     128 MiB; the no=20, nv=80 problems fit with dozens of vectors);
+ *   - the work is enqueued on the context's stream and the call returns
+ *     without waiting: outputs are valid in stream order.
+ * Every call on a GPU uses that GPU's one region and leaves the last call's
+ * contents in it; the kernels overwrite every element of the region they
+ * read, so nothing has to start at zero.  Calls whose work overlaps on one
+ * GPU (other streams, other contexts, other host threads) race on the
+ * region: order them on one stream. */
+#define RID_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+RID_API rid_status rid_apply_operator_noalloc(rid_problem* prob, int32_t op, int32_t precision, int32_t nvec,
+                                              const double* x_dev, double* y_dev, double* y2_dev);
+
 /* ---- eigen-solve (Sec. 2.1; Eqs. TDA, Casida) ---------------------------
  * The k lowest roots in ascending order into omega_host[k].  TDA: x_dev
  * (k x N, optional) gets unit-norm eigenvectors.  RPA: x_dev and y_dev

@@ -37,6 +37,7 @@ RID_PRECISION_FP64, RID_PRECISION_MIXED = 0, 1
 RID_TDA, RID_RPA = 0, 1
 RID_OP_A, RID_OP_APB_AMB, RID_OP_T, RID_OP_TPM = 0, 1, 2, 3
 RID_MAX_HISTORY = 128
+RID_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -141,6 +142,7 @@ PROTOTYPES = {
     "rid_problem_window": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
     "rid_solve_opts_default": (None, [ctypes.POINTER(rid_solve_opts)]),
     "rid_apply_operator": (I32, [P, I32, I32, I32, P, P, P]),
+    "rid_apply_operator_noalloc": (I32, [P, I32, I32, I32, P, P, P]),
     "rid_eigen_solve": (I32, [P, ctypes.POINTER(rid_solve_opts), I32, I32, DP, P, P, DP,
                               ctypes.POINTER(rid_stats)]),
     "rid_response_solve": (I32, [P, ctypes.POINTER(rid_solve_opts), I32, P, I32, DP, DP, P, DP,

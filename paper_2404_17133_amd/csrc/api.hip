@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -43,6 +44,30 @@ rid_status guarded(rid_context* ctx, F&& f) {
 }
 
 void use_device(rid_context* ctx) { RID_HIP(hipSetDevice(ctx->device)); }
+
+// Fixed device scratch of rid_apply_operator_noalloc.  In host code the
+// array's name stands for a host-side shadow, not a device address: the
+// device address of each GPU's copy is looked up once per device (in
+// rid_context_create, with that device current) and only that address is
+// ever handed to kernels.
+__device__ __align__(256) unsigned char scratch[RID_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (the device must be current).
+void* scratch_for_device(int device) {
+  RID_CHECK(device >= 0 && device < kMaxDevices, RID_ERR_NO_DEVICE, "device ordinal above the library's limit");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    RID_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    RID_CHECK(ptr != nullptr, RID_ERR_HIP, "no device address for the fixed scratch");
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -106,8 +131,11 @@ rid_status rid_context_create(int32_t device, void* hip_stream, const rid_alloca
     RID_HIP(hipGetDeviceProperties(&prop, device));
     RID_CHECK(std::strncmp(prop.gcnArchName, "gfx950", 6) == 0, RID_ERR_NO_DEVICE,
               std::string("library built for gfx950, device is ") + prop.gcnArchName);
+    RID_HIP(hipSetDevice(device));
+    void* scr = scratch_for_device(device);
     rid_context* c = new rid_context();
     c->device = device;
+    c->scratch = scr;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->alloc = *alloc;
     *out = c;
@@ -276,6 +304,34 @@ rid_status rid_apply_operator(rid_problem* prob, int32_t op, int32_t precision, 
     use_device(ctx);
     rid::apply_operator(prob, kind, prec, nvec, x_dev, y_dev, y2_dev);
     RID_HIP(hipStreamSynchronize(ctx->stream));
+    return RID_OK;
+  });
+}
+
+rid_status rid_apply_operator_noalloc(rid_problem* prob, int32_t op, int32_t precision, int32_t nvec,
+                                      const double* x_dev, double* y_dev, double* y2_dev) {
+  if (!prob) return RID_ERR_INVALID_ARG;
+  rid_context* ctx = prob->ctx;
+  return guarded(ctx, [&]() -> rid_status {
+    RID_CHECK(op >= RID_OP_A && op <= RID_OP_TPM, RID_ERR_INVALID_ARG, "unknown operator");
+    RID_CHECK(precision >= RID_F64 && precision <= RID_BF16, RID_ERR_INVALID_ARG, "unknown precision");
+    RID_CHECK(nvec >= 0, RID_ERR_SHAPE, "nvec must be >= 0");
+    if (nvec == 0) return RID_OK;
+    RID_CHECK(x_dev && y_dev, RID_ERR_INVALID_ARG, "null vector pointer");
+    const bool pair = op == RID_OP_APB_AMB || op == RID_OP_TPM;
+    RID_CHECK(!pair || y2_dev, RID_ERR_INVALID_ARG, "pair operators need y2");
+    RID_CHECK(ctx->scratch != nullptr, RID_ERR_INTERNAL, "fixed scratch not set up");
+    const int kind = op == RID_OP_A ? rid::OPK_A : op == RID_OP_APB_AMB ? rid::OPK_PAIR
+                   : op == RID_OP_T ? rid::OPK_T : rid::OPK_TPAIR;
+    const int prec = precision == RID_F64 ? rid::PREC_F64 : precision == RID_F32 ? rid::PREC_F32 : rid::PREC_BF16;
+    use_device(ctx);
+    rid::Arena arena;
+    arena.base = static_cast<char*>(ctx->scratch);
+    arena.cap = RID_NOALLOC_SCRATCH_BYTES;
+    // an eighth of the region per exchange chunk, at most 16 partial sums
+    const rid::OpLimits lim{(long)(RID_NOALLOC_SCRATCH_BYTES / 8), 16};
+    rid::apply_operator_fixed(prob, kind, prec, nvec, x_dev, y_dev, y2_dev, arena, lim);
+    RID_HIP(hipGetLastError());
     return RID_OK;
   });
 }

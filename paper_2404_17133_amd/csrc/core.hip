@@ -114,7 +114,21 @@ hipStream_t thread_stream() { return tl_stream; }
 ThreadStream::ThreadStream(hipStream_t s) : prev(tl_stream) { tl_stream = s; }
 ThreadStream::~ThreadStream() { tl_stream = prev; }
 
+void* Arena::take(size_t n) {
+  const size_t want = (std::max<size_t>(n, 256) + 255) & ~(size_t)255;
+  RID_CHECK(want <= cap - used, RID_ERR_SHAPE,
+            "product needs more scratch than the fixed region holds (" + std::to_string(cap >> 20) + " MiB)");
+  void* q = base + used;
+  used += want;
+  return q;
+}
+
 void DevBuf::release() {
+  if (arena) {  // slices of a fixed region are never returned
+    p = nullptr;
+    bytes = 0;
+    return;
+  }
   if (p && ctx) {
     bool park = false;
     {
@@ -203,6 +217,11 @@ DeferFree::~DeferFree() {
 
 void DevBuf::ensure(size_t n) {
   if (n <= bytes && p) return;
+  if (arena) {
+    p = arena->take(n);
+    bytes = std::max<size_t>(n, 256);
+    return;
+  }
   release();
   size_t want = std::max<size_t>(n, 256);
   p = dev_alloc(ctx, want);
@@ -294,14 +313,24 @@ struct GemmChoice {
 // tile, which rests on timings, does not change a single bit of the result,
 // and two runs of the same solve agree exactly.
 template <typename E>
-GemmChoice plan_for(int cfg, long M, long N, int nz, int np, int K, bool reduction) {
+GemmChoice plan_for(int cfg, long M, long N, int nz, int np, int K, bool reduction, int max_splits = 64) {
   if (!reduction) return GemmChoice{cfg, 1, np};
   constexpr int ref = 1;  // 64x64
   int bm = 0, bn = 0;
   gemm_config_tile<typename GemmTag<E>::type>(ref, &bm, &bn);
   const long tiles = ceil_div_l(M, bm) * ceil_div_l(N, bn) * nz;
-  const SplitPlan sp = choose_splits(tiles, np, K, gemm_slots<E>(ref));
+  const SplitPlan sp = choose_splits(tiles, np, K, gemm_slots<E>(ref), max_splits);
   return GemmChoice{cfg, sp.nsub, sp.pps};
+}
+
+// The tile configuration without tuning: 128x128 when it fills the chip,
+// 64x64 otherwise.
+template <typename E>
+GemmChoice default_choice(long M, long N, int nz, int np, int K, bool reduction, int max_splits) {
+  GemmChoice best = plan_for<E>(0, M, N, nz, np, K, reduction, max_splits);
+  const long t128 = ceil_div_l(M, 128) * ceil_div_l(N, 128) * nz * best.nsub;
+  if (t128 < gemm_slots<E>(0) / 2) best = plan_for<E>(1, M, N, nz, np, K, reduction, max_splits);
+  return best;
 }
 
 // Bytes of exchange intermediate (S^P or Q^P) per chunk of the auxiliary
@@ -344,10 +373,7 @@ GemmChoice tuned(rid_context* ctx, int family, long M, long N, int nz, int np, i
   }
   GemmChoice best = plan_for<E>(0, M, N, nz, np, K, reduction);
   if (!autotune_enabled()) {
-    // without tuning: the 128x128 tile when it fills the chip, else 64x64
-    static const int bm = 128;
-    const long t128 = ceil_div_l(M, bm) * ceil_div_l(N, bm) * nz * best.nsub;
-    if (t128 < gemm_slots<E>(0) / 2) best = plan_for<E>(1, M, N, nz, np, K, reduction);
+    best = default_choice<E>(M, N, nz, np, K, reduction, 64);
     launch(best);
   } else {
     hipEvent_t a, b;
@@ -478,10 +504,15 @@ struct Stage {
 // launches it alone.  Returns the choice.
 template <typename E>
 GemmChoice plan_or_tune(rid_context* ctx, Stage<E>& stage, int family, GemmParams p, long M, long N, int nz, int np,
-                        int K, bool reduction, hipStream_t st) {
+                        int K, bool reduction, hipStream_t st, const OpLimits* lim) {
   typedef typename GemmTag<E>::type G;
-  const TuneKey key{family, (int)sizeof(E), M, N, nz, np, K};
   GemmChoice ch;
+  if (lim) {  // fixed scratch: no tuning runs, no shared cache
+    ch = default_choice<E>(M, N, nz, np, K, reduction, lim->max_splits);
+    stage.add(p, nz, ch);
+    return ch;
+  }
+  const TuneKey key{family, (int)sizeof(E), M, N, nz, np, K};
   if (tuned_lookup(ctx, key, &ch)) {
     stage.add(p, nz, ch);
     return ch;
@@ -612,15 +643,20 @@ struct JobPlan {
 
 // Products of jobs that share element type E and operator (outer or ris).
 template <typename E>
-void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipStream_t st) {
+void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipStream_t st, const OpLimits* lim) {
   typedef typename AccOf<E>::type Acc;
   const std::string pre = ris ? "ris_" : "";
   const double esz = (double)sizeof(E), asz = (double)sizeof(Acc);
   std::vector<JobPlan<E>> pl(jobs.size());
+  // a product under fixed limits records no profiling events
+  rid_context* pctx = lim ? nullptr : ctx;
+  const int split_cap = lim ? lim->max_splits : 64;
 
-  // 1. plans and vector layouts in the compute type
+  // 1. plans and every scratch buffer of every job (all sized before the
+  // first launch, so that a fixed region too small fails before any work),
+  // then the vector layouts in the compute type
   {
-    ProfScope ps(ctx, st, (pre + "prep").c_str(), 0.0, 0.0);
+    ProfScope ps(pctx, st, (pre + "prep").c_str(), 0.0, 0.0);
     for (size_t q = 0; q < jobs.size(); ++q) {
       JobPlan<E>& J = pl[q];
       OpJob* j = jobs[q];
@@ -650,8 +686,15 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         w.xa.ensure(sizeof(E) * (size_t)J.nvec * J.no_a * J.kv);
         w.xt.ensure(sizeof(E) * (size_t)J.nvec * J.no_a * J.kv);
       }
-      prep_x<E>(j->x, J.nvec, J.no, J.nv, J.i0, J.no_a, J.nv_a, J.kv, w.xc.as<E>(), J.exch ? w.xa.as<E>() : nullptr,
-                J.exch ? w.xt.as<E>() : nullptr, st);
+      if (J.naux_j > 0) {
+        // Coulomb: partial sums for the largest split count any plan can
+        // pick, the reduced t, J and the partials of its P ranges
+        w.tpart.ensure(sizeof(Acc) * (size_t)std::min(J.no, split_cap) * J.nvec * J.naux_j);
+        w.t64.ensure(sizeof(double) * (size_t)J.nvec * J.naux_j);
+        w.jbuf.ensure(sizeof(double) * J.nvec * J.n);
+        const int ns = coul_bwd_splits(J.n, J.nvec, J.naux_j);
+        if (ns > 1) w.jpart.ensure(sizeof(double) * (size_t)ns * J.nvec * J.n);
+      }
       J.rows = (long)J.no_a * J.nvec;  // exchange output rows (i, v)
       J.part_elems = J.rows * J.nv_a;
       if (J.exch) {
@@ -660,15 +703,16 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         J.s_per_p = (long)J.no_a * J.nvec * J.kv;
         J.q_per_p = (long)J.no_a * J.nvec * J.no_a;
         const long per_p = std::max(J.s_per_p, J.pair ? J.q_per_p : 0L);
-        const long target = chunk_target_bytes();  // bytes of intermediate per chunk of the auxiliary index
+        // bytes of intermediate per chunk of the auxiliary index
+        const long target = lim ? lim->chunk_bytes : chunk_target_bytes();
         J.pc = (int)std::max<long>(1, std::min<long>(std::max(J.nk, J.nk_lr),
                                                       target / std::max<long>(1, per_p * (long)sizeof(E))));
         J.nch_sr = ceil_div(J.nk, J.pc);
         J.nchunks = J.nch_sr + ceil_div(J.nk_lr, J.pc);
         int max_splits = 1;
         for (int cfg = 0; cfg < gemm_num_configs<typename GemmTag<E>::type>(); ++cfg) {
-          max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.kv, true).nsub);
-          max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.no_a, true).nsub);
+          max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.kv, true, split_cap).nsub);
+          max_splits = std::max(max_splits, plan_for<E>(cfg, J.rows, J.nv_a, 1, J.pc, J.no_a, true, split_cap).nsub);
         }
         w.s.ensure(sizeof(E) * (size_t)J.pc * J.s_per_p);
         w.wpart.ensure(sizeof(Acc) * (size_t)max_splits * J.part_elems);
@@ -680,16 +724,22 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
     }
   }
 
+  {
+    ProfScope ps(pctx, st, (pre + "prep").c_str(), 0.0, 0.0);
+    for (JobPlan<E>& J : pl) {
+      OpWork& w = *J.j->work;
+      prep_x<E>(J.j->x, J.nvec, J.no, J.nv, J.i0, J.no_a, J.nv_a, J.kv, w.xc.as<E>(), J.exch ? w.xa.as<E>() : nullptr,
+                J.exch ? w.xt.as<E>() : nullptr, st);
+    }
+  }
+
   // 2. Coulomb forward: t[v][P] = sum_i sum_a Xc[v][i nv + a] B[P][i nv + a]
   {
     Stage<E> stage;
-    ProfScope ps(ctx, st, (pre + "coul_fwd").c_str(), 0.0, 0.0);
+    ProfScope ps(pctx, st, (pre + "coul_fwd").c_str(), 0.0, 0.0);
     for (JobPlan<E>& J : pl) {
       if (J.naux_j <= 0) continue;
       OpWork& w = *J.j->work;
-      // partial buffer sized for the largest split count any plan can pick
-      w.tpart.ensure(sizeof(Acc) * (size_t)std::min(J.no, 64) * J.nvec * J.naux_j);
-      w.t64.ensure(sizeof(double) * (size_t)J.nvec * J.naux_j);
       GemmParams g{};
       g.A = w.xc.p;
       g.B = J.ov.b_ia;
@@ -710,20 +760,18 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
       g.mode = GEMM_PARTIAL_SET;
       ps.flops += 2.0 * J.nvec * J.naux_j * (double)J.n;
       ps.bytes += esz * ((double)J.naux_j * J.n + (double)J.nvec * J.n);
-      J.ns_coul = plan_or_tune<E>(ctx, stage, GF_COUL, g, J.nvec, J.naux_j, 1, J.no, J.nv, true, st).nsub;
+      J.ns_coul = plan_or_tune<E>(ctx, stage, GF_COUL, g, J.nvec, J.naux_j, 1, J.no, J.nv, true, st, lim).nsub;
     }
     stage.launch(ctx, GF_COUL, st);
   }
   {
-    ProfScope ps(ctx, st, (pre + "coul_bwd").c_str(), 0.0, 0.0);
+    ProfScope ps(pctx, st, (pre + "coul_bwd").c_str(), 0.0, 0.0);
     for (JobPlan<E>& J : pl) {
       if (J.naux_j <= 0) continue;
       OpWork& w = *J.j->work;
       reduce_splits<Acc>(w.tpart.as<Acc>(), J.ns_coul, (long)J.nvec * J.naux_j, (long)J.nvec * J.naux_j,
                          w.t64.as<double>(), st);
-      w.jbuf.ensure(sizeof(double) * J.nvec * J.n);
       const int ns = coul_bwd_splits(J.n, J.nvec, J.naux_j);
-      if (ns > 1) w.jpart.ensure(sizeof(double) * (size_t)ns * J.nvec * J.n);
       coul_bwd<E>(w.t64.as<double>(), J.ov.b_ia, J.naux_j, J.n, J.nvec, w.jbuf.as<double>(),
                   ns > 1 ? w.jpart.as<double>() : nullptr, ns > 1 ? w.jpart.bytes / sizeof(double) : 0, st);
       ps.flops += 2.0 * J.nvec * J.naux_j * (double)J.n;
@@ -743,7 +791,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
   for (int c = 0; c < max_chunks; ++c) {
     {  // S^P = B^P_ij (window) x Xt
       Stage<E> stage;
-      ProfScope ps(ctx, st, (pre + "exch_s").c_str(), 0.0, 0.0);
+      ProfScope ps(pctx, st, (pre + "exch_s").c_str(), 0.0, 0.0);
       for (JobPlan<E>& J : pl) {
         if (!J.exch || c >= J.nchunks) continue;
         const typename JobPlan<E>::Chunk ck = J.chunk(c);
@@ -772,7 +820,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
           g.np = 1;
           g.mode = GEMM_STORE;
           g.order = ORDER_MN;
-          plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, g.M, g.N, 1, 1, J.no_a, true, st);
+          plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, g.M, g.N, 1, 1, J.no_a, true, st, lim);
         } else {
           // one product per P, run back to back per workgroup (Xt shared)
           g.A = ck.ij + (long)c0 * J.no * J.no + (long)J.i0 * J.no + J.i0;
@@ -782,14 +830,14 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
           g.sCs = J.s_per_p;
           g.mode = GEMM_STORE_EACH;
           g.order = ORDER_ZIN;  // each XCD keeps its share of Xt in L2 across all P
-          plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.kv, 1, pcc, J.no_a, true, st);
+          plan_or_tune<E>(ctx, stage, GF_EXCH_S, g, J.no_a, (long)J.nvec * J.kv, 1, pcc, J.no_a, true, st, lim);
         }
       }
       stage.launch(ctx, GF_EXCH_S, st);
     }
     {  // W += sum_P S^P B^P_ab (window)
       Stage<E> stage;
-      ProfScope ps(ctx, st, (pre + "exch_w").c_str(), 0.0, 0.0);
+      ProfScope ps(pctx, st, (pre + "exch_w").c_str(), 0.0, 0.0);
       for (JobPlan<E>& J : pl) {
         if (!J.exch || c >= J.nchunks) continue;
         const typename JobPlan<E>::Chunk ck = J.chunk(c);
@@ -819,7 +867,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         ps.bytes += esz * ((double)pcc * J.s_per_p + (double)pcc * J.nv_a * J.nv_a) +
                     asz * J.part_elems * (first ? 1.0 : 2.0);
         if (first)
-          J.cw = plan_or_tune<E>(ctx, stage, GF_EXCH_W, g, J.rows, J.nv_a, 1, pcc, J.kv, true, st);
+          J.cw = plan_or_tune<E>(ctx, stage, GF_EXCH_W, g, J.rows, J.nv_a, 1, pcc, J.kv, true, st, lim);
         else
           stage.add(g, 1, J.cw);
       }
@@ -828,7 +876,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
     if (!any_pair) continue;
     {  // Q^P = B^P_ia (window) x Xa^T
       Stage<E> stage;
-      ProfScope ps(ctx, st, (pre + "exch_q").c_str(), 0.0, 0.0);
+      ProfScope ps(pctx, st, (pre + "exch_q").c_str(), 0.0, 0.0);
       for (JobPlan<E>& J : pl) {
         if (!J.exch || !J.pair || c >= J.nchunks) continue;
         const typename JobPlan<E>::Chunk ck = J.chunk(c);
@@ -855,7 +903,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
           g.np = 1;
           g.mode = GEMM_STORE;
           g.order = ORDER_MN;
-          plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, g.M, g.N, 1, 1, J.kv, true, st);
+          plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, g.M, g.N, 1, 1, J.kv, true, st, lim);
         } else {
           g.A = ck.ia + (long)c0 * J.n + (long)J.i0 * J.nv;
           g.M = J.no_a;
@@ -864,14 +912,14 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
           g.sCs = J.q_per_p;
           g.mode = GEMM_STORE_EACH;
           g.order = ORDER_ZIN;
-          plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, 1, pcc, J.kv, true, st);
+          plan_or_tune<E>(ctx, stage, GF_EXCH_Q, g, J.no_a, (long)J.nvec * J.no_a, 1, pcc, J.kv, true, st, lim);
         }
       }
       stage.launch(ctx, GF_EXCH_Q, st);
     }
     {  // W' += sum_P Q^P B^P_ja (window), B_ja read from the transposed copy
       Stage<E> stage;
-      ProfScope ps(ctx, st, (pre + "exch_wp").c_str(), 0.0, 0.0);
+      ProfScope ps(pctx, st, (pre + "exch_wp").c_str(), 0.0, 0.0);
       for (JobPlan<E>& J : pl) {
         if (!J.exch || !J.pair || c >= J.nchunks) continue;
         const typename JobPlan<E>::Chunk ck = J.chunk(c);
@@ -901,7 +949,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
         ps.bytes += esz * ((double)pcc * J.q_per_p + (double)pcc * J.nv_a * J.no_a) +
                     asz * J.part_elems * (first ? 1.0 : 2.0);
         if (first)
-          J.cwp = plan_or_tune<E>(ctx, stage, GF_EXCH_WP, g, J.rows, J.nv_a, 1, pcc, J.no_a, true, st);
+          J.cwp = plan_or_tune<E>(ctx, stage, GF_EXCH_WP, g, J.rows, J.nv_a, 1, pcc, J.no_a, true, st, lim);
         else
           stage.add(g, 1, J.cwp);
       }
@@ -910,7 +958,7 @@ void run_group(rid_context* ctx, const std::vector<OpJob*>& jobs, bool ris, hipS
   }
 
   // 4. combine in f64
-  ProfScope ps(ctx, st, (pre + "combine").c_str(), 0.0, 0.0);
+  ProfScope ps(pctx, st, (pre + "combine").c_str(), 0.0, 0.0);
   for (JobPlan<E>& J : pl) {
     OpJob* j = J.j;
     OpWork& w = *j->work;
@@ -952,7 +1000,7 @@ void prepare_problem(rid_problem* P, const rid_solve_opts& o) {
   }
 }
 
-void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st) {
+void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st, const OpLimits* lim) {
   for (int prec = PREC_F64; prec <= PREC_BF16; ++prec)
     for (int r = 0; r < 2; ++r) {
       const bool ris = r == 1;
@@ -964,11 +1012,11 @@ void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st) {
       }
       if (sel.empty()) continue;
       if (prec == PREC_F64)
-        run_group<double>(ctx, sel, ris, st);
+        run_group<double>(ctx, sel, ris, st, lim);
       else if (prec == PREC_F32)
-        run_group<float>(ctx, sel, ris, st);
+        run_group<float>(ctx, sel, ris, st, lim);
       else
-        run_group<uint16_t>(ctx, sel, ris, st);
+        run_group<uint16_t>(ctx, sel, ris, st, lim);
     }
 }
 
@@ -987,6 +1035,43 @@ void apply_operator(rid_problem* P, int kind, int prec, int nvec, const double* 
   j.stream = P->ctx->stream;
   OpJob* jp = &j;
   run_jobs(P->ctx, &jp, 1, P->ctx->stream);
+}
+
+bool operator_copies_ready(const rid_problem* P, int kind, int prec) {
+  const bool ris = kind == OPK_T || kind == OPK_TPAIR;
+  if (prec == PREC_BF16) return P->bris_ia16.p != nullptr;
+  if (prec == PREC_F32) return P->b_ai32.p != nullptr;
+  // FP64: the transposed copies ensure_f64_aux makes
+  if (!ris) {
+    if (P->b_dt == RID_F64 && !P->b_ai64.p) return false;
+    if (P->lr.rows > 0 && P->lr.dt == RID_F64 && !P->lr.ai64.p) return false;
+    return true;
+  }
+  if (P->bris_dt == RID_F64 && P->bris_ia && P->naux_ris_k > 0 && !P->bris_ai64.p) return false;
+  if (P->rislr.rows > 0 && P->rislr.dt == RID_F64 && !P->rislr.ai64.p) return false;
+  return true;
+}
+
+void apply_operator_fixed(rid_problem* P, int kind, int prec, int nvec, const double* x, double* y, double* y2,
+                          Arena& arena, const OpLimits& lim) {
+  check_operator(P, kind, prec);
+  RID_CHECK(operator_copies_ready(P, kind, prec), RID_ERR_INVALID_ARG,
+            "the problem's tensor copies for this operator and precision are not made yet (a first "
+            "rid_apply_operator or solve in this precision makes them)");
+  if (nvec <= 0) return;
+  OpWork work(&arena);
+  OpJob j;
+  j.P = P;
+  j.kind = kind;
+  j.prec = prec;
+  j.nvec = nvec;
+  j.x = x;
+  j.y = y;
+  j.y2 = y2;
+  j.work = &work;
+  j.stream = P->ctx->stream;
+  OpJob* jp = &j;
+  run_jobs(P->ctx, &jp, 1, P->ctx->stream, &lim);
 }
 
 Batcher::Batcher(rid_context* ctx) : ctx_(ctx) {

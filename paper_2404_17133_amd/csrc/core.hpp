@@ -85,6 +85,7 @@ struct rid_context {
   std::vector<hipEvent_t> grave_events;  // recycled
   uint64_t grave_bytes = 0;
   rid::DescRing* ring = nullptr;  // grouped-GEMM descriptor staging
+  void* scratch = nullptr;  // device address of this device's fixed scratch (rid_apply_operator_noalloc)
   ~rid_context();
 };
 
@@ -126,16 +127,30 @@ struct DeferFree {
   ~DeferFree();
 };
 
-// Owning device buffer from the context's allocator.
+// A fixed device region handed out front to back (never freed piecewise):
+// the scratch of an operator product that may not allocate.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t n);  // throws RID_ERR_SHAPE when the region is exhausted
+};
+
+// Owning device buffer from the context's allocator, or (with an arena) a
+// slice of a fixed region that is never returned.
 struct DevBuf {
   rid_context* ctx = nullptr;
+  Arena* arena = nullptr;
   void* p = nullptr;
   size_t bytes = 0;
   DevBuf() = default;
   explicit DevBuf(rid_context* c) : ctx(c) {}
+  explicit DevBuf(Arena* a) : arena(a) {}
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : ctx(o.ctx), p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : ctx(o.ctx), arena(o.arena), p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
   ~DevBuf() { release(); }
   void release();
   // Grow to at least n bytes (contents are not preserved).
@@ -149,6 +164,8 @@ struct OpWork {
   DevBuf xc, xa, xt, tpart, t64, jbuf, jpart, s, q, wpart, wppart;
   explicit OpWork(rid_context* c)
       : xc(c), xa(c), xt(c), tpart(c), t64(c), jbuf(c), jpart(c), s(c), q(c), wpart(c), wppart(c) {}
+  explicit OpWork(Arena* a)
+      : xc(a), xa(a), xt(a), tpart(a), t64(a), jbuf(a), jpart(a), s(a), q(a), wpart(a), wppart(a) {}
   size_t bytes() const {
     return xc.bytes + xa.bytes + xt.bytes + tpart.bytes + t64.bytes + jbuf.bytes + jpart.bytes + s.bytes + q.bytes +
            wpart.bytes + wppart.bytes;
@@ -242,6 +259,27 @@ enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
 // Runs on the context stream with the problem's own scratch.
 void apply_operator(rid_problem* P, int kind, int prec, int nvec, const double* x, double* y, double* y2);
 
+// Limits of a product whose scratch is a fixed region: exchange chunks of
+// at most chunk_bytes of intermediate, at most max_splits partial sums per
+// reduction, no autotuning (the default tile rule; results differ from a
+// tuned product only by the rounding of the split sums), no profiling
+// events, no host synchronisation.
+struct OpLimits {
+  long chunk_bytes;
+  int max_splits;
+};
+
+// apply_operator with every scratch buffer carved from `arena` (nothing is
+// allocated) under `lim`.  The problem's tensor copies for this operator and
+// precision must exist already (RID_ERR_INVALID_ARG otherwise); a region too
+// small gives RID_ERR_SHAPE before any kernel is launched.  Enqueued on the
+// context stream; returns without waiting.
+void apply_operator_fixed(rid_problem* P, int kind, int prec, int nvec, const double* x, double* y, double* y2,
+                          Arena& arena, const OpLimits& lim);
+
+// Whether the tensor copies that products of (kind, prec) read already exist.
+bool operator_copies_ready(const rid_problem* P, int kind, int prec);
+
 // One operator product request.
 struct OpJob {
   rid_problem* P = nullptr;
@@ -261,7 +299,7 @@ struct OpJob {
 // Run the products of several jobs on stream st.  Every GEMM stage of all
 // jobs goes out as one grouped launch per tile configuration; each job's
 // result is what it would be alone.  Jobs must have been checked.
-void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st);
+void run_jobs(rid_context* ctx, OpJob* const* jobs, int n, hipStream_t st, const OpLimits* lim = nullptr);
 
 // Collects operator products from solves running on several host threads
 // and streams, and runs whatever is waiting as one grouped product on a

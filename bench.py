@@ -82,6 +82,86 @@ def cpu_baseline(p, n_mv_per_step, roots_per_step, naux_sample=200):
     }
 
 
+def oracle_solves(precond, reps=3, no100=False):
+    """The FP64 oracle's whole step -- full-TDDFT 10 lowest roots plus the
+    static polarizability of 3 dipole right-hand sides, the same algorithm
+    and preconditioner as the GPU step -- timed end to end on the no=20
+    molecule (median of `reps` solves with all BLAS threads, and with one),
+    and with no100 once on the no=100 molecule (minutes of CPU time).
+    Returns a dict for the JSON line."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import OracleProblem, eigen_rpa, polarizability
+    from synth import config_sizes, make_dipoles, make_problem
+
+    def one(name):
+        no, nv, naux, nris, seed = config_sizes(name)
+        p = make_problem(no, nv, naux, nris, seed=seed)
+        op = OracleProblem.from_arrays(p.numpy())
+        pm = make_dipoles(p, 3).numpy().T
+
+        def run():
+            t0 = time.perf_counter()
+            e = eigen_rpa(op, 10, precond)
+            a = polarizability(op, pm, [0.0], precond)
+            if not (e.converged and a.converged):
+                raise RuntimeError("oracle solve did not converge")
+            return time.perf_counter() - t0, e.n_iter, a.n_iter
+        return run
+
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    out = {"what": "oracle full-TDDFT 10 roots + static alpha (3 RHS), %s preconditioner, tolerance 1e-5, "
+                   "time.perf_counter per whole step" % ("rid" if precond == "ris" else "diagonal"),
+           "blas": sorted({"%s (%s)" % (i.get("internal_api"), i.get("version")) for i in threadpool_info()})}
+    run0 = one("c0")
+    run0()  # warm (imports, first BLAS calls)
+    ts = [run0() for _ in range(reps)]
+    out["no20_all_threads"] = {"threads": int(threads), "median_s": round(float(np.median([t[0] for t in ts])), 3),
+                               "roots_per_s": round(13.0 / float(np.median([t[0] for t in ts])), 3),
+                               "eigen_iters": ts[0][1], "alpha_iters": ts[0][2], "repeats": reps}
+    with threadpool_limits(1):
+        ts1 = [run0() for _ in range(reps)]
+    out["no20_one_thread"] = {"threads": 1, "median_s": round(float(np.median([t[0] for t in ts1])), 3),
+                              "roots_per_s": round(13.0 / float(np.median([t[0] for t in ts1])), 3)}
+    if not no100:
+        return out
+    t1 = one("c1")()
+    out["no100_all_threads"] = {"threads": int(threads), "seconds": round(t1[0], 2),
+                                "roots_per_s": round(13.0 / t1[0], 4), "eigen_iters": t1[1], "alpha_iters": t1[2],
+                                "repeats": 1}
+    return out
+
+
+def per_root_error(size, omega, alpha):
+    """Errors of a GPU step against the stored FP64 oracle results of the
+    same molecule (tolerance 1e-8; tests/golden/make_golden.py): per root
+    |Omega - Omega_oracle| in Ha, and the largest |alpha - alpha_oracle|
+    relative to max |alpha_oracle| of the static polarizability."""
+    import numpy as np
+
+    path = os.path.join(ROOT, "tests", "golden", "oracle_%s.json" % size)
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    ref = np.array(g["rpa_omega"])
+    a0 = np.array(g["alpha"][g["alpha_omegas"].index(0.0)])
+    return {"omega_abs_err_Ha": [float(v) for v in np.abs(np.asarray(omega)[:len(ref)] - ref)],
+            "alpha_max_rel_err": float(np.abs(np.asarray(alpha) - a0).max() / np.abs(a0).max()),
+            "oracle": "tests/golden/oracle_%s.json (FP64 CPU oracle, tolerance %g)" % (size, g["tol"])}
+
+
+def residual_slope(history):
+    """Least-squares slope of log10 of the largest residual norm per outer
+    iteration (the convergence rate the paper plots for one molecule)."""
+    import numpy as np
+
+    h = np.asarray([v for v in history if v > 0])
+    if len(h) < 2:
+        return None
+    return round(float(np.polyfit(np.arange(len(h)), np.log10(h), 1)[0]), 4)
+
+
 def measured_traffic(family: str, dtype: str, size: str = "c2"):
     """Calibrated HBM bytes per launch of `family` from the committed counter
     summary of the no=200 workload, or None for another workload, when the
@@ -339,6 +419,99 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def served_leg(n_req=12, no_max=100, slots=8, load=0.7, budget_gb=96):
+    """A short served stream beside the single-molecule step: n_req requests
+    of synth.serve_trace (no log-uniform in [20, no_max]), kept in FP64 so
+    that both paths serve the very same molecules.  Mixed precision first
+    with all requests at once (saturated rate), then as Poisson arrivals at
+    `load` x that rate; FP64 saturated, then replaying the mixed run's
+    arrival times.  Returns roots/s and latency percentiles of each."""
+    import numpy as np
+    import torch
+
+    import paper_2404_17133_amd as rid
+    from synth import serve_trace
+
+    trace = serve_trace(n_req, no_max=no_max)
+    ctx = rid.Context(0)
+    probs, dips = [], []
+    for d in trace:
+        pr, dp = f64_problem(rid, ctx, d, dipoles=d["kind"] != "eigen")
+        probs.append(pr)
+        dips.append(dp)
+    torch.cuda.synchronize()
+
+    def requests(precision):
+        opts = rid.default_opts("ris", precision)
+        reqs, keeps, roots = [], [], 0
+        for d, dp in zip(trace, dips):
+            if d["kind"] == "eigen":
+                r, kp = rid.make_request("eigen", opts, k=d["k"], mode=d["mode"])
+                roots += d["k"]
+            else:
+                r, kp = rid.make_request("polarizability", opts, p=dp, omegas=d["omegas"])
+                roots += 3 * len(d["omegas"])
+            reqs.append(r)
+            keeps.append(kp)
+        return reqs, keeps, roots
+
+    def serve(reqs, keeps, gaps):
+        srv = rid.Server(ctx, hbm_budget_bytes=budget_gb << 30, max_slots=slots)
+        tick = []
+        tnext = time.perf_counter()
+        for i, (pr, r) in enumerate(zip(probs, reqs)):
+            tnext += gaps[i]
+            delay = tnext - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tick.append(srv.submit(pr, r, keep=keeps[i]))
+        res = [srv.wait(t) for t in tick]
+        srv.close()
+        bad = [x["status"] for x in res if x["status"] != 0]
+        if bad:
+            raise RuntimeError("served requests failed: %s" % bad)
+        lat = np.array([(x["t_done_ms"] - x["t_arrival_ms"]) * 1e-3 for x in res])
+        span = (max(x["t_done_ms"] for x in res) - min(x["t_arrival_ms"] for x in res)) * 1e-3
+        return lat, span, res
+
+    def pct(lat):
+        return {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)}
+
+    out = {"workload": "%d served requests, no log-uniform in [20, %d], 70%% TDA/RPA eigen k 5..20, 30%% "
+                       "polarizability 3 RHS x 3 frequencies, rid preconditioner, %d slots; molecules in FP64, "
+                       "served by both paths" % (n_req, no_max, slots)}
+    legs = {}
+    for precision in ("mixed", "fp64"):
+        reqs, keeps, roots = requests(precision)
+        serve(reqs, keeps, [0.0] * n_req)  # warm: tensor copies and tuned shapes
+        lat_s, span_s, res_s = serve(reqs, keeps, [0.0] * n_req)
+        if precision == "mixed":
+            rate = n_req / span_s
+            gaps = [d["gap"] / (load * rate) for d in trace]
+        lat_p, span_p, _ = serve(reqs, keeps, gaps)
+        legs[precision] = res_s
+        out[precision] = {"saturated_roots_per_s": round(roots / span_s, 4), "saturated_s": round(span_s, 3),
+                          "saturated_latency_s": pct(lat_s),
+                          "poisson_roots_per_s": round(roots / span_p, 4), "poisson_latency_s": pct(lat_p)}
+        log("served %s: saturated %.2f s (%.2f roots/s), arrivals p50 %.2f s p99 %.2f s" % (
+            precision, span_s, roots / span_s, np.percentile(lat_p, 50), np.percentile(lat_p, 99)))
+    out["roots_per_pass"] = roots
+    out["arrivals"] = "Poisson at %.2f x the mixed saturated request rate (%.4f req/s), the same times for both" % (
+        load, load * rate)
+    out["speedup_mixed_vs_fp64_saturated"] = round(out["mixed"]["saturated_roots_per_s"]
+                                                   / out["fp64"]["saturated_roots_per_s"], 3)
+    dom, dal = 0.0, 0.0
+    for a, b in zip(legs["mixed"], legs["fp64"]):
+        if "omega" in a:
+            dom = max(dom, float(np.max(np.abs(a["omega"] - b["omega"]))))
+        if "alpha" in a:
+            dal = max(dal, float(np.max(np.abs(a["alpha"] - b["alpha"]) / np.abs(b["alpha"]).max())))
+    out["max_abs_omega_diff_Ha"] = dom
+    out["max_rel_alpha_diff"] = dal
+    ctx.close()
+    return out
+
+
 SWEEP = [
     # label, preconditioner, Naux_ris (None: config value), exchange rows (None: Naux_ris/9), source, noise, window
     ("diagonal", "diag", None, None, "svd", 0.05, True),
@@ -473,8 +646,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precond", default="ris", choices=["ris", "diag"])
-    ap.add_argument("--fp64-steps", type=int, default=1, help="steps of the FP64 GPU comparison (0 = skip)")
+    ap.add_argument("--fp64-steps", type=int, default=2, help="timed steps of the FP64 GPU comparison (0 = skip)")
+    ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed FP64 steps before those")
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="single: requests of the short served leg, mixed and FP64 (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serve", action="store_true", help="single: skip the served leg")
+    ap.add_argument("--cpu-no100", action="store_true",
+                    help="also time one oracle step on the no=100 molecule (minutes of CPU time)")
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--m-max", type=int, default=0,
                     help="single: subspace size that triggers a restart (0: the library default)")
@@ -499,7 +678,9 @@ def main():
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent requests")
     ap.add_argument("--hbm-budget-gb", type=int, default=96, help="serve: admission budget")
     args = ap.parse_args()
-    if args.workload in ("batch", "serve"):
+    if args.no_serve:
+        args.serve_requests = 0
+    if args.workload in ("batch", "serve") or args.serve_requests > 0:
         # many concurrent solve streams: more hardware queues keep them from
         # queueing behind each other (set before the HIP runtime starts)
         os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
@@ -629,10 +810,27 @@ def main():
         "solve": {"eigen_iters": last[0]["stats"]["n_iter"], "eigen_n_mv": last[0]["stats"]["n_mv"],
                   "eigen_inner_mv": last[0]["stats"]["n_inner_mv"],
                   "alpha_iters": last[1]["stats"]["n_iter"],
-                  "omega": [round(float(x), 10) for x in last[0]["omega"]]},
+                  "omega": [round(float(x), 10) for x in last[0]["omega"]],
+                  # share of the solve time spent in the preconditioner and
+                  # the ris initial guess (the paper's cost target: 1-2 %)
+                  "precond_time_share": {
+                      "eigen": round(last[0]["stats"]["t_precond_ms"] / max(last[0]["stats"]["t_total_ms"], 1e-9), 4),
+                      "alpha": round(last[1]["stats"]["t_precond_ms"] / max(last[1]["stats"]["t_total_ms"], 1e-9),
+                                     4)},
+                  "residual_log10_slope_per_iter": {"eigen": residual_slope(last[0]["stats"]["history"]),
+                                                    "alpha": residual_slope(last[1]["stats"]["history"])}},
     }
+    err = per_root_error(args.size, last[0]["omega"], last[1]["alpha"][0])
+    if err is not None:
+        out["per_root_err_vs_oracle"] = {"mixed": err}
 
     if args.fp64_steps > 0:
+        # untimed FP64 steps first: the FP64 launch shapes are tuned there,
+        # not inside the timed steps
+        for w in range(args.fp64_warmup):
+            step("fp64")
+            torch.cuda.synchronize()
+            log("fp64 warmup step %d done" % w)
         lat64 = []
         for s in range(args.fp64_steps):
             ts = time.perf_counter()
@@ -643,13 +841,25 @@ def main():
         v64 = roots_per_step * len(lat64) / sum(lat64)
         dom = float(np.max(np.abs(last[0]["omega"] - e64["omega"])))
         dal = float(np.max(np.abs(last[1]["alpha"] - a64["alpha"])) / np.max(np.abs(a64["alpha"])))
-        out["fp64_gpu"] = {"value": round(v64, 4), "unit": "roots/s",
-                           "latency_s_p50": round(float(np.percentile(lat64, 50)), 3),
+        out["fp64_gpu"] = {"value": round(v64, 4), "unit": "roots/s", "steps": len(lat64),
+                           "warmup": args.fp64_warmup,
+                           "latency_s": {"p50": round(float(np.percentile(lat64, 50)), 3),
+                                         "p99": round(float(np.percentile(lat64, 99)), 3)},
                            "speedup_mixed_vs_fp64": round(value / v64, 3),
                            "max_abs_omega_diff_Ha": dom, "max_rel_alpha_diff": dal}
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(p, n_mv, roots_per_step)
+        err64 = per_root_error(args.size, e64["omega"], a64["alpha"][0])
+        if err64 is not None:
+            out["per_root_err_vs_oracle"]["fp64"] = err64
     ctx.close()
+    del prob
+    if args.serve_requests > 0:
+        out["served"] = served_leg(args.serve_requests)
+    if not args.no_cpu:
+        cb = cpu_baseline(p, n_mv, roots_per_step)
+        del p
+        torch.cuda.empty_cache()
+        cb["solves"] = oracle_solves(args.precond, no100=args.cpu_no100)
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

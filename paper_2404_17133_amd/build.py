@@ -21,7 +21,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librid.so")
 
-SOURCES = ["gemm.hip", "opkern.hip", "engkern.hip", "dense.hip", "core.hip", "engine.hip", "server.hip", "api.hip"]
+SOURCES = ["gemm.hip", "opkern.hip", "engkern.hip", "dense.hip", "core.hip", "sched.hip", "engine.hip", "server.hip",
+           "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -384,22 +384,19 @@ rid_status rid_profile_read(rid_context* ctx, rid_kernel_stat* out, int32_t cap,
     RID_CHECK(n && (out || cap == 0) && cap >= 0, RID_ERR_INVALID_ARG, "bad output arguments");
     use_device(ctx);
     RID_HIP(hipStreamSynchronize(ctx->stream));
-    rid::Profiler& p = ctx->prof;
-    p.resolve();
+    const auto fams = ctx->prof.take();
     int cnt = 0;
-    for (size_t f = 0; f < p.names.size(); ++f) {
-      if (p.acc[f].launches == 0) continue;
+    for (const auto& f : fams) {
       if (cnt < cap) {
         rid_kernel_stat& s = out[cnt];
         std::memset(&s, 0, sizeof(s));
-        std::strncpy(s.name, p.names[f].c_str(), sizeof(s.name) - 1);
-        s.launches = p.acc[f].launches;
-        s.total_ms = p.acc[f].ms;
-        s.flops = p.acc[f].flops;
-        s.bytes = p.acc[f].bytes;
+        std::strncpy(s.name, f.first.c_str(), sizeof(s.name) - 1);
+        s.launches = f.second.launches;
+        s.total_ms = f.second.ms;
+        s.flops = f.second.flops;
+        s.bytes = f.second.bytes;
       }
       ++cnt;
-      p.acc[f] = rid::Profiler::Acc();
     }
     *n = cnt;
     return RID_OK;

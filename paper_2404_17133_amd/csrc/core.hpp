@@ -2,6 +2,7 @@
 // operator driver.  Internal C++ (no exceptions cross the C ABI).
 #pragma once
 
+#include <atomic>
 #include <condition_variable>
 #include <map>
 #include <thread>
@@ -24,7 +25,7 @@ struct Profiler {
     int64_t launches = 0;
     double ms = 0.0, flops = 0.0, bytes = 0.0;
   };
-  bool on = false;
+  std::atomic<bool> on{false};
   std::mutex mu;  // solves on several host threads share the profiler
   std::vector<std::string> names;
   std::map<std::string, int> ids;
@@ -33,7 +34,12 @@ struct Profiler {
   std::vector<Acc> acc;
   int family(const char* name);   // caller holds mu
   hipEvent_t get_event();         // caller holds mu
-  void resolve();  // streams must be idle
+  // Fold the records whose launches have completed into the totals (those
+  // still running stay for a later call); safe while solves record.
+  void resolve();
+  // resolve(), then the totals of every family with launches, which are
+  // reset; safe while solves record.
+  std::vector<std::pair<std::string, Acc>> take();
   ~Profiler();
 };
 
@@ -58,6 +64,7 @@ struct TuneVal {
 
 struct DescRing;
 class Batcher;
+void ring_free(DescRing* r);  // deletes a descriptor ring (null allowed)
 
 }  // namespace rid
 

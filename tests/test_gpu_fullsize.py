@@ -116,3 +116,37 @@ def test_c2_mixed_static_polarizability_residual_entries(c2):
         worst = max(worst, np.abs(apb_u + rhs).max() / np.linalg.norm(pn[v]))
     print("largest sampled relative residual entry:", worst, flush=True)
     assert worst < 1e-5
+
+
+def _golden_c2():
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_c2.json")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_c2_roots_and_alpha_against_stored_oracle(c2, precision):
+    """The benchmarked workload against the FP64 oracle run to 1e-8 on the
+    same molecule (tests/golden/oracle_c2.json, written by make_golden.py):
+    every one of the 10 full-TDDFT roots within 1e-6 Ha and the static
+    polarizability of the 3 dipole right-hand sides within 1e-5 relative, in
+    both precisions.  Root by root, so a skipped lower root (which a residual
+    check cannot see) fails."""
+    p, ctx, prob, host = c2
+    g = _golden_c2()
+    ref = np.array(g["rpa_omega"])
+    print("c2 oracle comparison", precision, flush=True)
+    out = prob.eigen(10, "rpa", "ris", precision, vectors=False)
+    assert out["status"] == 0
+    err = np.abs(out["omega"] - ref)
+    print("per-root |dOmega| (Ha):", err, flush=True)
+    assert np.all(err < 1e-6), err
+    pd = make_dipoles(p, 3)
+    a = prob.polarizability(pd, [0.0], "ris", precision)
+    assert a["status"] == 0
+    a0 = np.array(g["alpha"][0])
+    rel = np.abs(a["alpha"][0] - a0).max() / np.abs(a0).max()
+    print("alpha max relative error:", rel, flush=True)
+    assert rel < 1e-5, rel

@@ -258,6 +258,50 @@ RID_API rid_status rid_apply_operator(rid_problem* prob, int32_t op, int32_t pre
 RID_API rid_status rid_apply_operator_noalloc(rid_problem* prob, int32_t op, int32_t precision, int32_t nvec,
                                               const double* x_dev, double* y_dev, double* y2_dev);
 
+/* ---- auxiliary-basis tensors from a molecule (Sec. 2.2.2) ---------------
+ * The RI tensor of Eq. TDDFT-ris_approx, K^P_pq = (pq|P), J = (P|Q)^-1,
+ * factored as B = sqrt(kappa) L^-1 K with (P|Q) = L L^T, so that
+ * sum_P B^P_pq B^P_rs = kappa sum_PQ (pq|P) [(P|Q)^-1]_PQ (Q|rs); the three
+ * blocks of B are what rid_problem_desc takes.  Molecular orbitals
+ * p = sum_mu C_mu,p chi_mu over normalised s-type Gaussian atomic orbitals
+ * chi_mu (exponents per atom, centred on the atoms).  The auxiliary basis is
+ * either the list of shells given (nshell > 0: atom, angular momentum l <= 2,
+ * exponent), or the minimal basis of the ris model (nshell = 0): one shell
+ * of each l <= lmax on every atom with exponent theta / R_A^2 (the paper's
+ * rid preconditioner: lmax = 2, theta = 0.6).  Functions are ordered s
+ * shells first, then p (x, y, z), then d (real solid harmonics xy, xz, yz,
+ * x^2 - y^2, 2 z^2 - x^2 - y^2), shells in the order given (minimal basis:
+ * by atom); the leading naux_s rows of B are then the tensor of the s
+ * functions alone -- pass naux_s as rid_problem_desc.naux_ris_k for the
+ * (d, s) design of Sec. 3.2.  Lengths in bohr.  At most 1024 auxiliary
+ * functions; RID_ERR_INDEFINITE when (P|Q) is not positive definite. */
+typedef struct {
+  int32_t natom;
+  const double* coords_host;      /* natom x 3 */
+  const double* radius_host;      /* natom: R_A of the exponent rule (minimal basis) */
+  const int32_t* ao_count_host;   /* natom: s-type atomic orbitals on each atom */
+  const double* ao_exp_host;      /* nao exponents, atom by atom */
+  int32_t nao;
+  const double* mo_dev;           /* nao x (no + nv), row-major, device, FP64 */
+  int32_t no, nv;                 /* occupied orbitals first */
+  double kappa;                   /* scale of the Coulomb operator (> 0) */
+  int32_t nshell;                 /* > 0: the explicit shells below; 0: the minimal basis */
+  const int32_t* shell_atom_host;
+  const int32_t* shell_l_host;
+  const double* shell_exp_host;
+  double theta;                   /* minimal basis: exponent theta / R_A^2 */
+  int32_t lmax;                   /* minimal basis: highest angular momentum, 0..2 */
+} rid_aux_basis_desc;
+
+/* Number of auxiliary functions (naux) and of s functions (naux_s). */
+RID_API rid_status rid_aux_basis_size(const rid_aux_basis_desc* desc, int32_t* naux, int32_t* naux_s);
+/* Build b_ia (naux, no, nv), b_ij (naux, no, no), b_ab (naux, nv, nv) into
+ * the caller's FP64 device buffers, on the context stream; synchronous.
+ * Scratch (the integrals over atomic orbitals, naux * nao^2 doubles, and
+ * the transformed tensor) comes from the context's allocator. */
+RID_API rid_status rid_aux_tensor_build(rid_context* ctx, const rid_aux_basis_desc* desc, double* b_ia_dev,
+                                        double* b_ij_dev, double* b_ab_dev);
+
 /* ---- eigen-solve (Sec. 2.1; Eqs. TDA, Casida) ---------------------------
  * The k lowest roots in ascending order into omega_host[k].  TDA: x_dev
  * (k x N, optional) gets unit-norm eigenvectors.  RPA: x_dev and y_dev

@@ -12,9 +12,11 @@ from .solver import (  # noqa: F401
     Problem,
     RidError,
     Server,
+    aux_tensor,
     batch_solve,
     default_opts,
     make_request,
     make_result,
+    molecule_problem,
     request_footprint,
 )

@@ -120,6 +120,17 @@ class rid_result(ctypes.Structure):
     ]
 
 
+class rid_aux_basis_desc(ctypes.Structure):
+    _fields_ = [
+        ("natom", ctypes.c_int32), ("coords_host", ctypes.POINTER(ctypes.c_double)),
+        ("radius_host", ctypes.POINTER(ctypes.c_double)), ("ao_count_host", ctypes.POINTER(ctypes.c_int32)),
+        ("ao_exp_host", ctypes.POINTER(ctypes.c_double)), ("nao", ctypes.c_int32), ("mo_dev", ctypes.c_void_p),
+        ("no", ctypes.c_int32), ("nv", ctypes.c_int32), ("kappa", ctypes.c_double), ("nshell", ctypes.c_int32),
+        ("shell_atom_host", ctypes.POINTER(ctypes.c_int32)), ("shell_l_host", ctypes.POINTER(ctypes.c_int32)),
+        ("shell_exp_host", ctypes.POINTER(ctypes.c_double)), ("theta", ctypes.c_double), ("lmax", ctypes.c_int32),
+    ]
+
+
 class rid_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_int32)]
 
@@ -143,6 +154,8 @@ PROTOTYPES = {
     "rid_solve_opts_default": (None, [ctypes.POINTER(rid_solve_opts)]),
     "rid_apply_operator": (I32, [P, I32, I32, I32, P, P, P]),
     "rid_apply_operator_noalloc": (I32, [P, I32, I32, I32, P, P, P]),
+    "rid_aux_basis_size": (I32, [ctypes.POINTER(rid_aux_basis_desc), ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+    "rid_aux_tensor_build": (I32, [P, ctypes.POINTER(rid_aux_basis_desc), P, P, P]),
     "rid_eigen_solve": (I32, [P, ctypes.POINTER(rid_solve_opts), I32, I32, DP, P, P, DP,
                               ctypes.POINTER(rid_stats)]),
     "rid_response_solve": (I32, [P, ctypes.POINTER(rid_solve_opts), I32, P, I32, DP, DP, P, DP,

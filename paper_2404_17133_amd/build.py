@@ -22,7 +22,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librid.so")
 
 SOURCES = ["gemm.hip", "opkern.hip", "engkern.hip", "dense.hip", "core.hip", "sched.hip", "engine.hip", "server.hip",
-           "api.hip"]
+           "auxint.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 
+#include "auxint.hpp"
 #include "core.hpp"
 #include "engine.hpp"
 #include "server.hpp"
@@ -332,6 +333,28 @@ rid_status rid_apply_operator_noalloc(rid_problem* prob, int32_t op, int32_t pre
     const rid::OpLimits lim{(long)(RID_NOALLOC_SCRATCH_BYTES / 8), 16};
     rid::apply_operator_fixed(prob, kind, prec, nvec, x_dev, y_dev, y2_dev, arena, lim);
     RID_HIP(hipGetLastError());
+    return RID_OK;
+  });
+}
+
+rid_status rid_aux_basis_size(const rid_aux_basis_desc* desc, int32_t* naux, int32_t* naux_s) {
+  return guarded(nullptr, [&]() -> rid_status {
+    RID_CHECK(desc && naux && naux_s, RID_ERR_INVALID_ARG, "null argument");
+    int n = 0, ns = 0;
+    rid::aux_basis_size(*desc, &n, &ns);
+    *naux = n;
+    *naux_s = ns;
+    return RID_OK;
+  });
+}
+
+rid_status rid_aux_tensor_build(rid_context* ctx, const rid_aux_basis_desc* desc, double* b_ia_dev, double* b_ij_dev,
+                                double* b_ab_dev) {
+  if (!ctx) return RID_ERR_INVALID_ARG;
+  return guarded(ctx, [&]() -> rid_status {
+    RID_CHECK(desc, RID_ERR_INVALID_ARG, "desc is NULL");
+    use_device(ctx);
+    rid::aux_tensor_build(ctx, *desc, b_ia_dev, b_ij_dev, b_ab_dev);
     return RID_OK;
   });
 }

@@ -283,6 +283,69 @@ class Problem:
             pass
 
 
+def _aux_desc(mol, mo: torch.Tensor, minimal: bool, theta: float, lmax: int):
+    """rid_aux_basis_desc of a molecule (synth.Molecule fields) and the host
+    arrays it points to (kept alive by the caller)."""
+    d = B.rid_aux_basis_desc()
+    keep = []
+
+    def host(a, dtype, ptr):
+        a = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ptr))
+
+    d.natom = len(mol.radius)
+    d.coords_host = host(mol.coords, np.float64, ctypes.c_double)
+    d.radius_host = host(mol.radius, np.float64, ctypes.c_double)
+    d.ao_count_host = host(mol.ao_count, np.int32, ctypes.c_int32)
+    d.ao_exp_host = host(mol.ao_exp, np.float64, ctypes.c_double)
+    d.nao = len(mol.ao_exp)
+    d.mo_dev = mo.data_ptr()
+    d.no, d.nv = mol.no, mol.nv
+    d.kappa = mol.kappa
+    if minimal:
+        d.nshell = 0
+        d.theta = theta
+        d.lmax = lmax
+    else:
+        d.nshell = len(mol.shell_exp)
+        d.shell_atom_host = host(mol.shell_atom, np.int32, ctypes.c_int32)
+        d.shell_l_host = host(mol.shell_l, np.int32, ctypes.c_int32)
+        d.shell_exp_host = host(mol.shell_exp, np.float64, ctypes.c_double)
+    return d, keep
+
+
+def aux_tensor(ctx: Context, mol, minimal: bool = True, theta: float = 0.6, lmax: int = 2):
+    """The RI tensor of a molecule's auxiliary basis, built on the device:
+    the minimal basis of the ris model (exponents theta / R_A^2, shells up
+    to lmax) or, with minimal=False, the molecule's full shell list.
+    Returns (b_ia, b_ij, b_ab, naux_s) as float64 device tensors."""
+    dev = torch.device("cuda", ctx.device)
+    mo = torch.as_tensor(np.ascontiguousarray(mol.mo), dtype=torch.float64, device=dev)
+    d, keep = _aux_desc(mol, mo, minimal, theta, lmax)
+    naux, ns = ctypes.c_int32(), ctypes.c_int32()
+    s = B.lib.rid_aux_basis_size(ctypes.byref(d), ctypes.byref(naux), ctypes.byref(ns))
+    if s != B.RID_OK:
+        raise RidError(s, B.lib.rid_last_error(None).decode())
+    n = naux.value
+    bia = torch.empty((n, mol.no, mol.nv), dtype=torch.float64, device=dev)
+    bij = torch.empty((n, mol.no, mol.no), dtype=torch.float64, device=dev)
+    bab = torch.empty((n, mol.nv, mol.nv), dtype=torch.float64, device=dev)
+    ctx.check(B.lib.rid_aux_tensor_build(ctx.handle, ctypes.byref(d), _ptr(bia), _ptr(bij), _ptr(bab)))
+    del keep
+    return bia, bij, bab, ns.value
+
+
+def molecule_problem(ctx: Context, mol, theta: float = 0.6, lmax: int = 2, a_x: float = 0.25,
+                     t_cut: float = float("inf")):
+    """A response problem built from a molecule on the device: A from the
+    molecule's full auxiliary basis, the ris model from the minimal one
+    (Coulomb: every function; exchange: the s functions)."""
+    fia, fij, fab, _ = aux_tensor(ctx, mol, minimal=False)
+    ria, rij, rab, ns = aux_tensor(ctx, mol, minimal=True, theta=theta, lmax=lmax)
+    return Problem(ctx, mol.eps_occ, mol.eps_vir, fia, fij, fab, a_x, ria, rij, rab, ns, t_cut)
+
+
 def make_request(kind: str, opts: B.rid_solve_opts, k: int = 0, mode: str = "tda",
                  p: Optional[torch.Tensor] = None, omegas: Optional[np.ndarray] = None,
                  x_out: Optional[torch.Tensor] = None, y_out: Optional[torch.Tensor] = None):

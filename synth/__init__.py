@@ -22,3 +22,4 @@ from .generate import (  # noqa: F401
     serve_trace,
     related_problem,
 )
+from .molecule import Molecule, make_molecule  # noqa: F401,E402

@@ -15,7 +15,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 NAMES = ["rid_allocator", "rid_problem_desc", "rid_solve_opts", "rid_stats", "rid_kernel_stat", "rid_request",
-         "rid_result", "rid_server_opts"]
+         "rid_result", "rid_server_opts", "rid_aux_basis_desc"]
 
 
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")

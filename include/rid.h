@@ -167,6 +167,14 @@ typedef struct {
    * orthonormalised (dependent directions dropped).  NULL / 0: none. */
   const double* guess_dev;
   int32_t n_guess;
+  /* 1: a solve that has the device to itself (not batched, not served, no
+   * profiling) runs each operator-product shape (block width) once
+   * directly and then as a captured HIP graph, replayed whenever that shape
+   * recurs on the problem -- in this solve and in later solves on the same
+   * problem.  The graph reads and writes staging copies of the vectors (two
+   * or three device copies per product), and is captured again when the
+   * problem's scratch has moved.  Results are bit-identical to 0. */
+  int32_t graphs;
 } rid_solve_opts;
 
 #define RID_MAX_HISTORY 128
@@ -327,10 +335,14 @@ RID_API rid_status rid_response_solve(rid_problem* prob, const rid_solve_opts* o
                               rid_stats* stats);
 
 /* ---- kernel profiling ---------------------------------------------------
- * While enabled, every launch of the library's main kernel families on the
- * context's stream is bracketed by HIP events.  rid_profile_read waits for
- * the stream, returns per-family totals (launch count, summed event time,
- * algorithmic FLOPs and bytes of the launches) and resets the counters.
+ * While enabled, every launch of the library's main kernel families is
+ * bracketed by HIP events on the stream it runs on (the recording costs a
+ * few percent of a solve's time; rid_profile_only limits it to one family).
+ * rid_profile_read waits for the context stream and returns per-family
+ * totals (launch count, summed event time, algorithmic FLOPs and bytes) of
+ * the launches that have completed, then resets them; launches still running
+ * on other streams (batched or served solves) count at a later read.  Both
+ * calls are safe while solves run on other threads.
  * Families: "exch_s" (S^P = B_ij X), "exch_w" (sum_P S^P B_ab), "exch_q"
  * (Q^P = B_ia X^T), "exch_wp" (sum_P Q^P B_ja), "coul_fwd", "coul_bwd",
  * "combine", "ris_*" (the same families of the ris model), "gram", "combo",
@@ -344,6 +356,10 @@ typedef struct {
 } rid_kernel_stat;
 
 RID_API rid_status rid_profile_enable(rid_context* ctx, int32_t on);
+/* Record only the launches of one family (for example "exch_w"), so that
+ * the timing of one kernel costs a fraction of the events; NULL: every
+ * family again.  Takes effect for launches enqueued after the call. */
+RID_API rid_status rid_profile_only(rid_context* ctx, const char* family);
 RID_API rid_status rid_profile_read(rid_context* ctx, rid_kernel_stat* out, int32_t cap, int32_t* n);
 
 /* ---- batched solves (many molecules per launch) -------------------------

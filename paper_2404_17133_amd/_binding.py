@@ -71,6 +71,7 @@ class rid_solve_opts(ctypes.Structure):
         ("max_iter", ctypes.c_int32), ("n_extra_init", ctypes.c_int32), ("inner_tol", ctypes.c_double),
         ("inner_max_iter", ctypes.c_int32), ("init_tol", ctypes.c_double), ("init_max_iter", ctypes.c_int32),
         ("m_max", ctypes.c_int32), ("guess_dev", ctypes.c_void_p), ("n_guess", ctypes.c_int32),
+        ("graphs", ctypes.c_int32),
     ]
 
 
@@ -162,6 +163,7 @@ PROTOTYPES = {
                                  ctypes.POINTER(rid_stats)]),
     "rid_profile_enable": (I32, [P, I32]),
     "rid_profile_read": (I32, [P, ctypes.POINTER(rid_kernel_stat), I32, ctypes.POINTER(I32)]),
+    "rid_profile_only": (I32, [P, ctypes.c_char_p]),
     "rid_batch_solve": (I32, [P, I32, PP, ctypes.POINTER(rid_request), ctypes.POINTER(rid_result)]),
     "rid_server_create": (I32, [P, ctypes.POINTER(rid_server_opts), PP]),
     "rid_server_submit": (I32, [P, P, ctypes.POINTER(rid_request), ctypes.POINTER(rid_result),

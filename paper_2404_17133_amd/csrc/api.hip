@@ -113,6 +113,7 @@ void rid_solve_opts_default(rid_solve_opts* o) {
   o->m_max = 0;
   o->guess_dev = nullptr;
   o->n_guess = 0;
+  o->graphs = 0;
 }
 
 rid_status rid_context_create(int32_t device, void* hip_stream, const rid_allocator* alloc, rid_context** out) {
@@ -397,6 +398,16 @@ rid_status rid_profile_enable(rid_context* ctx, int32_t on) {
     RID_HIP(hipStreamSynchronize(ctx->stream));
     ctx->prof.resolve();
     ctx->prof.on = on != 0;
+    return RID_OK;
+  });
+}
+
+rid_status rid_profile_only(rid_context* ctx, const char* family) {
+  if (!ctx) return RID_ERR_INVALID_ARG;
+  return guarded(ctx, [&]() -> rid_status {
+    RID_CHECK(!family || std::strlen(family) < 32, RID_ERR_INVALID_ARG, "family name too long");
+    std::lock_guard<std::mutex> g(ctx->prof.mu);
+    ctx->prof.only = family ? family : "";
     return RID_OK;
   });
 }

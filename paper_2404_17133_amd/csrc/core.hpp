@@ -27,6 +27,7 @@ struct Profiler {
   };
   std::atomic<bool> on{false};
   std::mutex mu;  // solves on several host threads share the profiler
+  std::string only;  // when set, the one family recorded (guarded by mu)
   std::vector<std::string> names;
   std::map<std::string, int> ids;
   std::vector<Rec> recs;
@@ -177,6 +178,39 @@ struct OpWork {
     return xc.bytes + xa.bytes + xt.bytes + tpart.bytes + t64.bytes + jbuf.bytes + jpart.bytes + s.bytes + q.bytes +
            wpart.bytes + wppart.bytes;
   }
+  std::vector<void*> addresses() const {
+    return {xc.p, xa.p, xt.p, tpart.p, t64.p, jbuf.p, jpart.p, s.p, q.p, wpart.p, wppart.p};
+  }
+};
+
+// An operator product of a single solve captured as a HIP graph: it reads
+// its input from and writes its outputs to staging buffers of its own, and
+// is replayed whenever the problem's solves ask for the same product shape
+// (kind, precision, block width) again.  The scratch it was captured with
+// is recorded: when the problem's scratch has been reallocated since, the
+// graph is captured anew.
+struct OpGraph {
+  int kind = 0, prec = 0, nvec = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  DevBuf x, y, y2;
+  std::vector<void*> work;  // addresses of the scratch buffers at capture
+  explicit OpGraph(rid_context* c) : x(c), y(c), y2(c) {}
+  OpGraph(const OpGraph&) = delete;
+  OpGraph& operator=(const OpGraph&) = delete;
+  ~OpGraph();
+};
+
+struct GraphCache {
+  std::vector<OpGraph*> graphs;
+  std::vector<long> seen;      // shapes run once without a graph (their GEMM shapes tuned)
+  std::vector<long> refused;   // shapes whose capture failed: always run directly
+  hipStream_t cap = nullptr;   // capture stream
+  GraphCache() = default;
+  GraphCache(const GraphCache&) = delete;
+  GraphCache& operator=(const GraphCache&) = delete;
+  void clear();
+  ~GraphCache();
 };
 
 // A view of one three-index tensor in element type E, as one operator uses it.
@@ -238,6 +272,7 @@ struct rid_problem {
   rid::DevBuf b_ia32, b_ij32, b_ab32, b_ai32;
   rid::DevBuf bris_ia16, bris_ij16, bris_ab16, bris_ai16;
   rid::OpWork work;
+  rid::GraphCache graphs;  // captured operator products of single solves (declared after work: freed first)
   // range-separated hybrid: exchange a_x (pq|rs) + b_x (pq|rs)^LR
   double b_x = 0.0;
   rid::LrSet lr, rislr;

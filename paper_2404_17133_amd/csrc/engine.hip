@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <numeric>
 
 #include "engine.hpp"
@@ -115,11 +116,87 @@ struct Eng {
       j.work = &own;
       j.ready = ready;
       batcher->apply(j);
-    } else {
+    } else if (!(use_graphs && graph_apply(kind, prec, nvec, x, y, y2))) {
       j.work = &P->work;
       OpJob* jp = &j;
       run_jobs(P->ctx, &jp, 1, st);
     }
+  }
+  // Replay (or capture, then replay) the product as a graph; false when
+  // the product has to run directly: the shape's first product (which sizes
+  // the scratch and tunes its GEMM shapes, so that the capture neither
+  // allocates nor times anything), profiling on, or a capture that failed.
+  bool use_graphs = false;
+  bool graph_apply(int kind, int prec, int nvec, const double* x, double* y, double* y2) {
+    rid_context* ctx = P->ctx;
+    if (ctx->prof.on) return false;
+    GraphCache& G = P->graphs;
+    const long key = ((long)kind * 4 + prec) * (1L << 24) + nvec;
+    if (std::find(G.refused.begin(), G.refused.end(), key) != G.refused.end()) return false;
+    OpGraph* g = nullptr;
+    for (OpGraph* h : G.graphs)
+      if (h->kind == kind && h->prec == prec && h->nvec == nvec) g = h;
+    if (g && g->work != P->work.addresses()) {
+      // the scratch was reallocated since the capture: capture again
+      G.graphs.erase(std::find(G.graphs.begin(), G.graphs.end(), g));
+      RID_HIP(hipStreamSynchronize(st));
+      delete g;
+      g = nullptr;
+    }
+    if (!g) {
+      if (std::find(G.seen.begin(), G.seen.end(), key) == G.seen.end()) {
+        G.seen.push_back(key);
+        return false;
+      }
+      if (!G.cap) RID_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+      const bool pair = kind == OPK_PAIR || kind == OPK_TPAIR;
+      std::unique_ptr<OpGraph> ng(new OpGraph(ctx));
+      ng->kind = kind;
+      ng->prec = prec;
+      ng->nvec = nvec;
+      ng->x.ensure(sizeof(double) * (size_t)nvec * N);
+      ng->y.ensure(sizeof(double) * (size_t)nvec * N);
+      if (pair) ng->y2.ensure(sizeof(double) * (size_t)nvec * N);
+      const std::vector<void*> before = P->work.addresses();
+      OpJob j;
+      j.P = P;
+      j.kind = kind;
+      j.prec = prec;
+      j.nvec = nvec;
+      j.x = ng->x.as<double>();
+      j.y = ng->y.as<double>();
+      j.y2 = pair ? ng->y2.as<double>() : nullptr;
+      j.stream = G.cap;
+      j.work = &P->work;
+      OpJob* jp = &j;
+      bool ok = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        try {
+          run_jobs(ctx, &jp, 1, G.cap);
+        } catch (const Error&) {
+          ok = false;
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(G.cap, &graph);
+        ng->graph = graph;
+        ok = ok && e == hipSuccess && graph != nullptr && P->work.addresses() == before;
+        if (ok) ok = hipGraphInstantiate(&ng->exec, ng->graph, nullptr, nullptr, 0) == hipSuccess;
+      }
+      if (!ok) {
+        (void)hipGetLastError();
+        G.refused.push_back(key);
+        return false;
+      }
+      ng->work = P->work.addresses();
+      g = ng.release();
+      G.graphs.push_back(g);
+    }
+    const size_t bytes = sizeof(double) * (size_t)nvec * N;
+    RID_HIP(hipMemcpyAsync(g->x.p, x, bytes, hipMemcpyDeviceToDevice, st));
+    RID_HIP(hipGraphLaunch(g->exec, st));
+    RID_HIP(hipMemcpyAsync(y, g->y.p, bytes, hipMemcpyDeviceToDevice, st));
+    if (y2) RID_HIP(hipMemcpyAsync(y2, g->y2.p, bytes, hipMemcpyDeviceToDevice, st));
+    return true;
   }
   RedScratch rs(int m, int n) {
     size_t need = std::max(gram_part_elems(m, n, N), (size_t)256 * std::max(n, 1));
@@ -1037,6 +1114,7 @@ void validate_opts(const rid_solve_opts& o, const rid_problem* P) {
   RID_CHECK(o.max_iter >= 1 && o.inner_max_iter >= 1 && o.init_max_iter >= 1, RID_ERR_INVALID_ARG,
             "iteration limits must be >= 1");
   RID_CHECK(o.m_max >= 0 && o.m_max <= 1000, RID_ERR_INVALID_ARG, "m_max must be in [0, 1000]");
+  RID_CHECK(o.graphs == 0 || o.graphs == 1, RID_ERR_INVALID_ARG, "graphs must be 0 or 1");
   if (o.precond == RID_PRECOND_RIS)
     RID_CHECK(P->has_ris(), RID_ERR_INVALID_ARG, "ris preconditioner needs a ris tensor");
   RID_CHECK(o.n_guess >= 0 && (o.n_guess == 0 || o.guess_dev != nullptr), RID_ERR_INVALID_ARG,
@@ -1057,6 +1135,7 @@ rid_status eigen_solve(rid_problem* P, const rid_solve_opts& o, int k, int mode,
   RID_CHECK(mode == RID_TDA || mode == RID_RPA, RID_ERR_INVALID_ARG, "bad mode");
   auto t_all = Clock::now();
   Eng E(P, &st, ex);
+  E.use_graphs = o.graphs != 0;
   rid_context* ctx = P->ctx;
   const bool ris = o.precond == RID_PRECOND_RIS;
   const int extra = o.n_extra_init >= 0 ? o.n_extra_init : (ris ? std::min(k, 3) : 8);
@@ -1248,6 +1327,7 @@ rid_status response_solve(rid_problem* P, const rid_solve_opts& o, int nrhs, con
   }
   auto t_all = Clock::now();
   Eng E(P, &st, ex);
+  E.use_graphs = o.graphs != 0;
   rid_context* ctx = P->ctx;
   const long N = P->n();
   const bool ris = o.precond == RID_PRECOND_RIS;

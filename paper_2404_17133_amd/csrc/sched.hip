@@ -80,6 +80,7 @@ ProfScope::ProfScope(rid_context* c, hipStream_t s, const char* name, double fl,
     : ctx(c), st(s), flops(fl), bytes(by) {
   if (!ctx || !ctx->prof.on) return;
   std::lock_guard<std::mutex> g(ctx->prof.mu);
+  if (!ctx->prof.only.empty() && ctx->prof.only != name) return;
   fam = ctx->prof.family(name);
   a = ctx->prof.get_event();
   RID_HIP(hipEventRecord(a, st));
@@ -310,6 +311,26 @@ void Batcher::loop(Lane& L) {
       j->finished = true;
     }
     cv_done_.notify_all();
+  }
+}
+
+OpGraph::~OpGraph() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+}
+
+void GraphCache::clear() {
+  for (OpGraph* g : graphs) delete g;
+  graphs.clear();
+  seen.clear();
+  refused.clear();
+}
+
+GraphCache::~GraphCache() {
+  clear();
+  if (cap) {
+    (void)hipStreamSynchronize(cap);
+    (void)hipStreamDestroy(cap);
   }
 }
 

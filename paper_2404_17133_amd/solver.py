@@ -84,6 +84,10 @@ class Context:
         """Enable or disable per-kernel-family launch timing."""
         self.check(B.lib.rid_profile_enable(self.handle, 1 if on else 0))
 
+    def profile_only(self, family: Optional[str] = None):
+        """Record only one kernel family's launches (None: all families)."""
+        self.check(B.lib.rid_profile_only(self.handle, family.encode() if family else None))
+
     def profile_read(self) -> dict:
         """Per-family totals since the last read: {name: dict(launches, ms, flops, bytes)}."""
         cap = 64

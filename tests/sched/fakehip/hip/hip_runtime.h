@@ -236,6 +236,12 @@ inline hipError_t hipHostFree(void* p) {
   return hipSuccess;
 }
 
+// graphs: only created and destroyed by the code built here
+typedef struct FakeGraph* hipGraph_t;
+typedef struct FakeGraphExec* hipGraphExec_t;
+inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
+
 // device intrinsics named in shared headers (never run on the CPU)
 template <typename T>
 inline T __shfl_xor(T v, int, int = 64) {

@@ -701,6 +701,8 @@ def main():
                     help="single: requests of the short served leg, mixed and FP64 (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="single: skip the served leg")
+    ap.add_argument("--tune-file", default=None,
+                    help="single: load GEMM tuning decisions from this file if it exists, save them after")
     ap.add_argument("--no-profile", action="store_true",
                     help="single: no per-kernel event timing in the timed steps (no roofline)")
     ap.add_argument("--graphs", type=int, default=0,
@@ -773,6 +775,11 @@ def main():
         del xs, ys
         log("copy probe: %d MiB read + %d MiB written" % (args.copy_probe, args.copy_probe))
     ctx = rid.Context(0)
+    if args.tune_file and os.path.exists(args.tune_file):
+        try:
+            log("tuning decisions loaded: %d" % ctx.tune_load(args.tune_file))
+        except rid.RidError as e:
+            log("tuning file not used: %s" % e)
     prob = rid.Problem.from_synth(ctx, p)
     k = args.k
     roots_per_step = k + pm.shape[0]
@@ -931,6 +938,8 @@ def main():
         err64 = per_root_error(args.size, e64["omega"], a64["alpha"][0])
         if err64 is not None:
             out["per_root_err_vs_oracle"]["fp64"] = err64
+    if args.tune_file:
+        log("tuning decisions saved: %d" % ctx.tune_save(args.tune_file))
     ctx.close()
     del prob
     if args.serve_requests > 0:

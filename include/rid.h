@@ -334,6 +334,19 @@ RID_API rid_status rid_response_solve(rid_problem* prob, const rid_solve_opts* o
                               double* alpha_host, double* u_dev, double* resid_host,
                               rid_stats* stats);
 
+/* ---- persistent tuning ----------------------------------------------------
+ * The first product of every GEMM launch shape on a context times the tile
+ * configurations and keeps the fastest.  rid_tune_save writes those
+ * decisions to a text file, rid_tune_load adds a file's decisions to a
+ * context (replacing its own decision for a shape listed in both), so that a new process
+ * skips the timing runs.  The file records the library build and the device
+ * architecture; a file from another build or device, or a malformed one, is
+ * refused with RID_ERR_INVALID_ARG and changes nothing.  count (optional)
+ * receives the number of decisions written or read.  Tuning never changes a
+ * result: every tile configuration sums in the same order. */
+RID_API rid_status rid_tune_save(rid_context* ctx, const char* path, int32_t* count);
+RID_API rid_status rid_tune_load(rid_context* ctx, const char* path, int32_t* count);
+
 /* ---- kernel profiling ---------------------------------------------------
  * While enabled, every launch of the library's main kernel families is
  * bracketed by HIP events on the stream it runs on (the recording costs a

@@ -164,6 +164,8 @@ PROTOTYPES = {
     "rid_profile_enable": (I32, [P, I32]),
     "rid_profile_read": (I32, [P, ctypes.POINTER(rid_kernel_stat), I32, ctypes.POINTER(I32)]),
     "rid_profile_only": (I32, [P, ctypes.c_char_p]),
+    "rid_tune_save": (I32, [P, ctypes.c_char_p, ctypes.POINTER(I32)]),
+    "rid_tune_load": (I32, [P, ctypes.c_char_p, ctypes.POINTER(I32)]),
     "rid_batch_solve": (I32, [P, I32, PP, ctypes.POINTER(rid_request), ctypes.POINTER(rid_result)]),
     "rid_server_create": (I32, [P, ctypes.POINTER(rid_server_opts), PP]),
     "rid_server_submit": (I32, [P, P, ctypes.POINTER(rid_request), ctypes.POINTER(rid_result),

@@ -39,9 +39,21 @@ FLAGS = [
 ]
 
 
+def build_id() -> str:
+    """Hash of the sources that decide GEMM launch shapes and their timing
+    (a tuning file records it: decisions of another build are refused)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("gemm.hip", "gemm.hpp", "core.hip", "core.hpp"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + ['-DRID_BUILD_ID="%s"' % build_id(), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l]
     if r.returncode != 0:

@@ -402,6 +402,26 @@ rid_status rid_profile_enable(rid_context* ctx, int32_t on) {
   });
 }
 
+rid_status rid_tune_save(rid_context* ctx, const char* path, int32_t* count) {
+  if (!ctx) return RID_ERR_INVALID_ARG;
+  return guarded(ctx, [&]() -> rid_status {
+    RID_CHECK(path, RID_ERR_INVALID_ARG, "path is NULL");
+    const int n = rid::tune_save(ctx, path);
+    if (count) *count = n;
+    return RID_OK;
+  });
+}
+
+rid_status rid_tune_load(rid_context* ctx, const char* path, int32_t* count) {
+  if (!ctx) return RID_ERR_INVALID_ARG;
+  return guarded(ctx, [&]() -> rid_status {
+    RID_CHECK(path, RID_ERR_INVALID_ARG, "path is NULL");
+    const int n = rid::tune_load(ctx, path);
+    if (count) *count = n;
+    return RID_OK;
+  });
+}
+
 rid_status rid_profile_only(rid_context* ctx, const char* family) {
   if (!ctx) return RID_ERR_INVALID_ARG;
   return guarded(ctx, [&]() -> rid_status {

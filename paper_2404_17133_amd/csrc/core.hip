@@ -15,6 +15,7 @@
 // combine kernel reduces in f64.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 
 #include "core.hpp"
@@ -993,5 +994,81 @@ void rid_problem::ensure_bf16() {
 namespace rid {
 
 void ring_free(DescRing* r) { delete r; }
+
+namespace {
+
+#ifndef RID_BUILD_ID
+#define RID_BUILD_ID "unknown"
+#endif
+
+std::string tune_header(int device) {
+  hipDeviceProp_t prop;
+  RID_HIP(hipGetDeviceProperties(&prop, device));
+  std::string arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ') c = '_';
+  return std::string("rid-tune 1 ") + RID_BUILD_ID + " " + arch;
+}
+
+}  // namespace
+
+int tune_save(rid_context* ctx, const char* path) {
+  const std::string head = tune_header(ctx->device);
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  FILE* f = std::fopen(path, "w");
+  RID_CHECK(f != nullptr, RID_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  std::fprintf(f, "%s\n", head.c_str());
+  for (const auto& kv : ctx->tune) {
+    const TuneKey& k = kv.first;
+    const TuneVal& v = kv.second;
+    std::fprintf(f, "%d %d %ld %ld %d %d %d %d %d %d\n", k.family, k.esz, k.M, k.N, k.nz, k.np, k.K, v.cfg, v.nsub,
+                 v.pps);
+  }
+  const bool ok = std::fclose(f) == 0;
+  RID_CHECK(ok, RID_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  return (int)ctx->tune.size();
+}
+
+int tune_load(rid_context* ctx, const char* path) {
+  const std::string head = tune_header(ctx->device);
+  FILE* f = std::fopen(path, "r");
+  RID_CHECK(f != nullptr, RID_ERR_INVALID_ARG, std::string("cannot read ") + path);
+  char line[512];
+  std::vector<std::pair<TuneKey, TuneVal>> got;
+  std::string err;
+  if (!std::fgets(line, sizeof(line), f)) {
+    err = "empty tuning file";
+  } else {
+    std::string h(line);
+    while (!h.empty() && (h.back() == '\n' || h.back() == '\r')) h.pop_back();
+    if (h != head) err = "tuning file made by another build or device (" + h + "; this is " + head + ")";
+  }
+  while (err.empty() && std::fgets(line, sizeof(line), f)) {
+    TuneKey k{};
+    TuneVal v{};
+    if (std::sscanf(line, "%d %d %ld %ld %d %d %d %d %d %d", &k.family, &k.esz, &k.M, &k.N, &k.nz, &k.np, &k.K, &v.cfg,
+                    &v.nsub, &v.pps) != 10) {
+      err = "malformed tuning line";
+      break;
+    }
+    // a known family and element type, a tile configuration of that type,
+    // and a split plan that covers its batches
+    const int ncfg = k.esz == 8   ? gemm_num_configs<double>()
+                     : k.esz == 4 ? gemm_num_configs<float>()
+                     : k.esz == 2 ? gemm_num_configs<bf16_t>()
+                                  : 0;
+    if (k.family < GF_GENERIC || k.family > GF_EXCH_WP || v.cfg < 0 || v.cfg >= ncfg || k.M < 1 || k.N < 1 ||
+        k.nz < 1 || k.K < 1 || k.np < 1 || v.nsub < 1 || v.pps < 1 || (long)v.nsub * v.pps < k.np) {
+      err = "tuning line with an invalid plan";
+      break;
+    }
+    got.emplace_back(k, v);
+  }
+  std::fclose(f);
+  RID_CHECK(err.empty(), RID_ERR_INVALID_ARG, err);
+  std::lock_guard<std::mutex> g(ctx->tune_mu);
+  for (const auto& kv : got) ctx->tune[kv.first] = kv.second;
+  return (int)got.size();
+}
 
 }  // namespace rid

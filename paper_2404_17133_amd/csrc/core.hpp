@@ -66,6 +66,10 @@ struct TuneVal {
 struct DescRing;
 class Batcher;
 void ring_free(DescRing* r);  // deletes a descriptor ring (null allowed)
+// Tuning decisions of a context to / from a text file (returns the count);
+// a file of another build or device is refused with RID_ERR_INVALID_ARG.
+int tune_save(rid_context* ctx, const char* path);
+int tune_load(rid_context* ctx, const char* path);
 
 }  // namespace rid
 

@@ -84,6 +84,18 @@ class Context:
         """Enable or disable per-kernel-family launch timing."""
         self.check(B.lib.rid_profile_enable(self.handle, 1 if on else 0))
 
+    def tune_save(self, path: str) -> int:
+        """Write the context's tuning decisions to a file; returns their count."""
+        n = ctypes.c_int32()
+        self.check(B.lib.rid_tune_save(self.handle, path.encode(), ctypes.byref(n)))
+        return n.value
+
+    def tune_load(self, path: str) -> int:
+        """Add a tuning file's decisions to the context; returns their count."""
+        n = ctypes.c_int32()
+        self.check(B.lib.rid_tune_load(self.handle, path.encode(), ctypes.byref(n)))
+        return n.value
+
     def profile_only(self, family: Optional[str] = None):
         """Record only one kernel family's launches (None: all families)."""
         self.check(B.lib.rid_profile_only(self.handle, family.encode() if family else None))

@@ -263,6 +263,11 @@ void launch_members(rid_context* ctx, const std::vector<GemmGroup>& mem, int cfg
     gemm_nt<G>(mem[0].p, mem[0].nz, mem[0].nsplit, st, cfg, family);
     return;
   }
+  // the descriptors go through reused pinned host slots, which a captured
+  // graph would read again at every replay: refuse the capture instead
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  RID_HIP(hipStreamIsCapturing(st, &cs));
+  RID_CHECK(cs == hipStreamCaptureStatusNone, RID_ERR_INTERNAL, "grouped GEMM launch under graph capture");
   {
     std::lock_guard<std::mutex> g(g_ring_mu);
     if (!ctx->ring) ctx->ring = new DescRing(ctx);

@@ -693,7 +693,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2,
+                    help="untimed steps; the first tunes the GEMM shapes, the last times every kernel family")
     ap.add_argument("--precond", default="ris", choices=["ris", "diag"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed steps of the FP64 GPU comparison (0 = skip)")
     ap.add_argument("--fp64-warmup", type=int, default=1, help="untimed FP64 steps before those")
@@ -906,7 +907,10 @@ def main():
                       "alpha": round(last[1]["stats"]["t_precond_ms"] / max(last[1]["stats"]["t_total_ms"], 1e-9),
                                      4)},
                   "residual_log10_slope_per_iter": {"eigen": residual_slope(last[0]["stats"]["history"]),
-                                                    "alpha": residual_slope(last[1]["stats"]["history"])}},
+                                                    "alpha": residual_slope(last[1]["stats"]["history"])},
+                  # largest residual norm after each outer iteration
+                  "residual_history": {"eigen": ["%.3e" % v for v in last[0]["stats"]["history"] if v > 0],
+                                       "alpha": ["%.3e" % v for v in last[1]["stats"]["history"] if v > 0]}},
     }
     err = per_root_error(args.size, last[0]["omega"], last[1]["alpha"][0])
     if err is not None:

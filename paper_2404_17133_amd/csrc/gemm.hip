@@ -12,6 +12,14 @@
 // group g (lanes sharing a row) takes the g-th slice of the stage, and MFMA
 // step s consumes the s-th element(s) of every group's slice.  Since A and B
 // use the same permutation the sum over K is unchanged.
+//
+// When K is not a multiple of the stage width (K = no = 200 in the exchange
+// S and W' products), a second form deals the chunks of a stage to the lane
+// groups in turn (group g takes chunks g, g + G, ...), so that the valid
+// chunks of a batch's last stage are the first chunk(s) of every group's
+// slice, and that stage runs only the MFMA steps of those chunks (K = 200:
+// 4 of the 16 steps of its last stage).  The form is chosen by K alone, so
+// every tile shape of a product sums in the same order.
 #include "gemm.hpp"
 #include "gemm_limits.hpp"
 
@@ -96,7 +104,7 @@ struct MinBlocks<double> {
 // the single-GEMM and the grouped kernels, so that a tile's arithmetic does
 // not depend on which kernel runs it.  Ends with every wave past the last
 // read of its LDS buffers, so that the next tile may refill them.
-template <typename T, int BM, int BN, int WM, int WN, bool VEC>
+template <typename T, int BM, int BN, int WM, int WN, bool VEC, bool IL>
 __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, int z, int split) {
   using At = Atom<T>;
   using E_t = typename At::elem_t;
@@ -116,6 +124,8 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
   constexpr int ANN = WN / At::AM;
   constexpr int SL = 8 / At::G;              // chunks per lane slice
   constexpr int KSTEPS = BK / At::G / At::E; // MFMA steps per stage
+  constexpr int SPC = KSTEPS / SL;           // MFMA steps per chunk of a slice
+  static_assert(SPC * SL == KSTEPS, "steps per chunk");
 
   __shared__ uint4 lds[2][ROWS * RS];
 
@@ -225,27 +235,35 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
 #pragma unroll
       for (int r = 0; r < At::NACC; ++r) acc[i][j][r] = acc_t(0);
 
-  auto compute = [&](int buf) {
+  // chunk c of lane group g's slice: chunk g*SL + c of the stage, or
+  // chunk c*G + g in the interleaved form
+  constexpr int CSTEP = IL ? At::G : 1;
+  const int cbase = IL ? g : g * SL;
+  // nc: chunks of every slice that hold valid K (all SL but in the last
+  // stage of a batch in the interleaved form)
+  auto compute = [&](int buf, int nc) {
     V_t fa[AMN][SL];
     V_t fb[ANN][SL];
 #pragma unroll
     for (int i = 0; i < AMN; ++i) {
-      const uint4* src = &lds[buf][(wm + i * At::AM + lr) * RS + g * SL];
+      const uint4* src = &lds[buf][(wm + i * At::AM + lr) * RS + cbase];
 #pragma unroll
-      for (int c = 0; c < SL; ++c) fa[i][c] = *reinterpret_cast<const V_t*>(src + c);
+      for (int c = 0; c < SL; ++c) fa[i][c] = *reinterpret_cast<const V_t*>(src + c * CSTEP);
     }
 #pragma unroll
     for (int j = 0; j < ANN; ++j) {
-      const uint4* src = &lds[buf][(BM + wn + j * At::AM + lr) * RS + g * SL];
+      const uint4* src = &lds[buf][(BM + wn + j * At::AM + lr) * RS + cbase];
 #pragma unroll
-      for (int c = 0; c < SL; ++c) fb[j][c] = *reinterpret_cast<const V_t*>(src + c);
+      for (int c = 0; c < SL; ++c) fb[j][c] = *reinterpret_cast<const V_t*>(src + c * CSTEP);
     }
 #pragma unroll
-    for (int s = 0; s < KSTEPS; ++s)
+    for (int s = 0; s < KSTEPS; ++s) {
+      if (IL && s % SPC == 0 && s / SPC >= nc) break;
 #pragma unroll
       for (int i = 0; i < AMN; ++i)
 #pragma unroll
         for (int j = 0; j < ANN; ++j) acc[i][j] = At::mma(At::op(fa[i], s), At::op(fb[j], s), acc[i][j]);
+    }
   };
 
   const acc_t alpha = (acc_t)p.alpha;
@@ -280,17 +298,24 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
   int kt_c = 0, p_c = pbeg;  // stage within its batch, and batch, of the stage being computed
   for (int t = 0; t < nstage; ++t) {
     if (t + 1 < nstage) gload(t + 1, pa);
-    compute(t & 1);
-    if (each && ++kt_c == nkt) {
-      store_tile(Ce + (long)p_c * p.sCs);
-#pragma unroll
-      for (int i = 0; i < AMN; ++i)
-#pragma unroll
-        for (int j = 0; j < ANN; ++j)
-#pragma unroll
-          for (int r = 0; r < At::NACC; ++r) acc[i][j][r] = acc_t(0);
+    int nc = SL;
+    if constexpr (IL) {
+      const int valid = K - kt_c * BK;  // K elements of this stage
+      if (valid < BK) nc = ((valid + VW - 1) / VW + At::G - 1) / At::G;
+    }
+    compute(t & 1, nc);
+    if (++kt_c == nkt) {
       kt_c = 0;
-      ++p_c;
+      if (each) {
+        store_tile(Ce + (long)p_c * p.sCs);
+#pragma unroll
+        for (int i = 0; i < AMN; ++i)
+#pragma unroll
+          for (int j = 0; j < ANN; ++j)
+#pragma unroll
+            for (int r = 0; r < At::NACC; ++r) acc[i][j][r] = acc_t(0);
+        ++p_c;
+      }
     }
     if (t + 1 < nstage) lstore((t + 1) & 1, pa);
     __syncthreads();
@@ -359,13 +384,13 @@ __device__ inline TileCoord walk_decode(int order, long t, int tiles_m, int tile
   return c;
 }
 
-template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
+template <typename T, int BM, int BN, int WM, int WN, bool VEC, bool IL, int FAM>
 __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmParams p, int nz, long total) {
   const int tiles_m = (p.M + BM - 1) / BM;
   const int tiles_n = (p.N + BN - 1) / BN;
   const int nsplit = (int)(total / ((long)tiles_m * tiles_n * nz));
   const TileCoord c = walk_decode(p.order, xcd_walk(blockIdx.x, total), tiles_m, tiles_n, nz, nsplit);
-  gemm_tile<T, BM, BN, WM, WN, VEC>(p, c.tm, c.tn, c.z, c.split);
+  gemm_tile<T, BM, BN, WM, WN, VEC, IL>(p, c.tm, c.tn, c.z, c.split);
 }
 
 // Device descriptor of one member of a grouped launch.
@@ -380,7 +405,7 @@ struct GroupDesc {
 // is a multiple of the XCD count, a workgroup stays on one XCD, and the
 // positions are re-mapped as in the single-GEMM kernel so that each XCD
 // covers one contiguous range of the concatenated walk.
-template <typename T, int BM, int BN, int WM, int WN, bool VEC, int FAM>
+template <typename T, int BM, int BN, int WM, int WN, bool VEC, bool IL, int FAM>
 __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_grouped_kernel(const GroupDesc* __restrict__ gd,
                                                                                int ngroups, long total) {
   for (long b = blockIdx.x; b < total; b += gridDim.x) {
@@ -396,7 +421,7 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_grouped_kernel(
     const GemmParams p = gd[lo].p;
     const TileCoord c =
         walk_decode(p.order, t - gd[lo].begin, gd[lo].tiles_m, gd[lo].tiles_n, gd[lo].nz, gd[lo].nsplit);
-    gemm_tile<T, BM, BN, WM, WN, VEC>(p, c.tm, c.tn, c.z, c.split);
+    gemm_tile<T, BM, BN, WM, WN, VEC, IL>(p, c.tm, c.tn, c.z, c.split);
   }
 }
 
@@ -419,34 +444,39 @@ struct Cfgs<bf16_t> {
   static constexpr TileCfg c[3] = {{128, 128}, {64, 64}, {128, 64}};
 };
 
+// Load form of a launch: 0 vector loads, 1 vector loads with interleaved
+// chunks (K not a multiple of the stage width), 2 scalar loads.
 template <typename T, int BM, int BN, int WM, int WN, int FAM>
-void launch_fam(const GemmParams& p, int nz, long total, bool vec, hipStream_t stream) {
-  if (vec)
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, true, FAM>), dim3((unsigned)total), dim3(256), 0, stream, p,
-                       nz, total);
+void launch_fam(const GemmParams& p, int nz, long total, int form, hipStream_t stream) {
+  if (form == 0)
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, true, false, FAM>), dim3((unsigned)total), dim3(256), 0,
+                       stream, p, nz, total);
+  else if (form == 1)
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, true, true, FAM>), dim3((unsigned)total), dim3(256), 0,
+                       stream, p, nz, total);
   else
-    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, false, FAM>), dim3((unsigned)total), dim3(256), 0, stream,
-                       p, nz, total);
+    hipLaunchKernelGGL((gemm_nt_kernel<T, BM, BN, WM, WN, false, false, FAM>), dim3((unsigned)total), dim3(256), 0,
+                       stream, p, nz, total);
 }
 
 template <typename T, int BM, int BN, int WM, int WN>
-void launch_cfg(const GemmParams& p, int nz, int nsplit, bool vec, hipStream_t stream, int family) {
+void launch_cfg(const GemmParams& p, int nz, int nsplit, int form, hipStream_t stream, int family) {
   const long total = (long)ceil_div(p.M, BM) * ceil_div(p.N, BN) * nz * nsplit;
   RID_CHECK(total < (1L << 31), RID_ERR_SHAPE, "gemm: grid too large");
   switch (family) {
-    case GF_COUL: launch_fam<T, BM, BN, WM, WN, GF_COUL>(p, nz, total, vec, stream); break;
-    case GF_EXCH_S: launch_fam<T, BM, BN, WM, WN, GF_EXCH_S>(p, nz, total, vec, stream); break;
-    case GF_EXCH_W: launch_fam<T, BM, BN, WM, WN, GF_EXCH_W>(p, nz, total, vec, stream); break;
-    case GF_EXCH_Q: launch_fam<T, BM, BN, WM, WN, GF_EXCH_Q>(p, nz, total, vec, stream); break;
-    case GF_EXCH_WP: launch_fam<T, BM, BN, WM, WN, GF_EXCH_WP>(p, nz, total, vec, stream); break;
-    default: launch_fam<T, BM, BN, WM, WN, GF_GENERIC>(p, nz, total, vec, stream); break;
+    case GF_COUL: launch_fam<T, BM, BN, WM, WN, GF_COUL>(p, nz, total, form, stream); break;
+    case GF_EXCH_S: launch_fam<T, BM, BN, WM, WN, GF_EXCH_S>(p, nz, total, form, stream); break;
+    case GF_EXCH_W: launch_fam<T, BM, BN, WM, WN, GF_EXCH_W>(p, nz, total, form, stream); break;
+    case GF_EXCH_Q: launch_fam<T, BM, BN, WM, WN, GF_EXCH_Q>(p, nz, total, form, stream); break;
+    case GF_EXCH_WP: launch_fam<T, BM, BN, WM, WN, GF_EXCH_WP>(p, nz, total, form, stream); break;
+    default: launch_fam<T, BM, BN, WM, WN, GF_GENERIC>(p, nz, total, form, stream); break;
   }
 }
 
-template <typename T, int BM, int BN, int WM, int WN, bool VEC>
+template <typename T, int BM, int BN, int WM, int WN, bool VEC, bool IL>
 void launch_grouped_fam(const GroupDesc* gd, int n, long total, int grid, int family, hipStream_t stream) {
-#define RID_GROUPED(F)                                                                                      \
-  hipLaunchKernelGGL((gemm_grouped_kernel<T, BM, BN, WM, WN, VEC, F>), dim3(grid), dim3(256), 0, stream, gd, n, \
+#define RID_GROUPED(F)                                                                                             \
+  hipLaunchKernelGGL((gemm_grouped_kernel<T, BM, BN, WM, WN, VEC, IL, F>), dim3(grid), dim3(256), 0, stream, gd, n, \
                      total)
   switch (family) {
     case GF_COUL: RID_GROUPED(GF_COUL); break;
@@ -460,11 +490,13 @@ void launch_grouped_fam(const GroupDesc* gd, int n, long total, int grid, int fa
 }
 
 template <typename T, int BM, int BN, int WM, int WN>
-void launch_grouped_cfg(const GroupDesc* gd, int n, long total, int grid, bool vec, int family, hipStream_t stream) {
-  if (vec)
-    launch_grouped_fam<T, BM, BN, WM, WN, true>(gd, n, total, grid, family, stream);
+void launch_grouped_cfg(const GroupDesc* gd, int n, long total, int grid, int form, int family, hipStream_t stream) {
+  if (form == 0)
+    launch_grouped_fam<T, BM, BN, WM, WN, true, false>(gd, n, total, grid, family, stream);
+  else if (form == 1)
+    launch_grouped_fam<T, BM, BN, WM, WN, true, true>(gd, n, total, grid, family, stream);
   else
-    launch_grouped_fam<T, BM, BN, WM, WN, false>(gd, n, total, grid, family, stream);
+    launch_grouped_fam<T, BM, BN, WM, WN, false, false>(gd, n, total, grid, family, stream);
 }
 
 template <typename T>
@@ -479,6 +511,13 @@ bool vec_ok(const GemmParams& p) {
          (p.sA1 % vw == 0) && (p.sA2 % vw == 0) && (p.sB1 % vw == 0) && (p.sB2 % vw == 0) &&
          ((uintptr_t)p.A % 16 == 0) && ((uintptr_t)p.B % 16 == 0) &&
          gemm_offsets_fit(p.lda, p.ldb, p.K, elem_size<T>());
+}
+
+// Load form (see launch_fam) of a GEMM.
+template <typename T>
+int load_form(const GemmParams& p) {
+  if (!vec_ok<T>(p)) return 2;
+  return p.K % (128 / elem_size<T>()) != 0 ? 1 : 0;
 }
 
 void check_params(const GemmParams& p, int nz, int nsplit) {
@@ -500,16 +539,16 @@ void gemm_grouped(const GemmGroup* mem, int n, int cfg, int family, void* desc_d
   RID_CHECK(cfg >= 0 && cfg < 3, RID_ERR_INTERNAL, "gemm: bad tile configuration");
   const int bm = Cfgs<T>::c[cfg].bm, bn = Cfgs<T>::c[cfg].bn;
   GroupDesc* hd = reinterpret_cast<GroupDesc*>(desc_host);
-  // vector-load members first, then the others: one launch per kind
-  int cnt[2] = {0, 0};
-  long total[2] = {0, 0};
-  for (int pass = 0; pass < 2; ++pass) {
+  // members by load form: one launch per form
+  int cnt[3] = {0, 0, 0};
+  long total[3] = {0, 0, 0};
+  for (int pass = 0; pass < 3; ++pass) {
     for (int i = 0; i < n; ++i) {
       const GemmParams& p = mem[i].p;
       if (p.M <= 0 || p.N <= 0 || mem[i].nz <= 0 || mem[i].nsplit <= 0) continue;
-      if (vec_ok<T>(p) != (pass == 0)) continue;
+      if (load_form<T>(p) != pass) continue;
       check_params(p, mem[i].nz, mem[i].nsplit);
-      GroupDesc& d = hd[cnt[0] + cnt[1]];
+      GroupDesc& d = hd[cnt[0] + cnt[1] + cnt[2]];
       d.p = p;
       d.tiles_m = ceil_div(p.M, bm);
       d.tiles_n = ceil_div(p.N, bn);
@@ -520,20 +559,20 @@ void gemm_grouped(const GemmGroup* mem, int n, int cfg, int family, void* desc_d
       ++cnt[pass];
     }
   }
-  const int used = cnt[0] + cnt[1];
+  const int used = cnt[0] + cnt[1] + cnt[2];
   if (used == 0) return;
   RID_HIP(hipMemcpyAsync(desc_dev, desc_host, sizeof(GroupDesc) * used, hipMemcpyHostToDevice, stream));
   const GroupDesc* dd = reinterpret_cast<const GroupDesc*>(desc_dev);
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0, first = 0; pass < 3; first += cnt[pass], ++pass) {
     if (cnt[pass] == 0) continue;
-    const GroupDesc* base = dd + (pass == 0 ? 0 : cnt[0]);
+    const GroupDesc* base = dd + first;
     // a multiple of the XCD count keeps every workgroup on one XCD
     const int cap = std::max(kXcds, grid_cap / kXcds * kXcds);
     const int grid = (int)std::min<long>(total[pass], cap);
     switch (cfg) {
-      case 0: launch_grouped_cfg<T, 128, 128, 64, 64>(base, cnt[pass], total[pass], grid, pass == 0, family, stream); break;
-      case 1: launch_grouped_cfg<T, 64, 64, 32, 32>(base, cnt[pass], total[pass], grid, pass == 0, family, stream); break;
-      default: launch_grouped_cfg<T, 128, 64, 64, 32>(base, cnt[pass], total[pass], grid, pass == 0, family, stream); break;
+      case 0: launch_grouped_cfg<T, 128, 128, 64, 64>(base, cnt[pass], total[pass], grid, pass, family, stream); break;
+      case 1: launch_grouped_cfg<T, 64, 64, 32, 32>(base, cnt[pass], total[pass], grid, pass, family, stream); break;
+      default: launch_grouped_cfg<T, 128, 64, 64, 32>(base, cnt[pass], total[pass], grid, pass, family, stream); break;
     }
     RID_HIP(hipGetLastError());
   }
@@ -553,7 +592,7 @@ template <typename T>
 void gemm_nt(const GemmParams& p, int nz, int nsplit, hipStream_t stream, int cfg, int family) {
   if (p.M <= 0 || p.N <= 0 || nz <= 0 || nsplit <= 0) return;
   check_params(p, nz, nsplit);
-  const bool vec = vec_ok<T>(p);
+  const int vec = load_form<T>(p);
   if (cfg < 0) {
     // default: big tiles when the output is large enough to fill the chip
     const long t128 = ceil_div_l(p.M, 128) * ceil_div_l(p.N, 128) * (long)nz * nsplit;

@@ -43,11 +43,14 @@ def gemm_source_hash() -> str:
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"gemm_nt_kernel<([^,]+), (\d+), (\d+), \d+, \d+, (\w+), (\d+)>", name)
+    # gemm_nt_kernel<type, BM, BN, WM, WN, vector loads, [interleaved chunks,] family>
+    m = re.search(r"gemm_nt_kernel<([^,]+), (\d+), (\d+), \d+, \d+, (\w+), (?:(\w+), )?(\d+)>", name)
     if m:
         t = m.group(1).replace("rid::", "")
-        return "gemm_nt<%s,%sx%s,%s> [%s]" % (t, m.group(2), m.group(3), "vec" if m.group(4) == "true" else "scalar",
-                                             FAMILIES.get(m.group(5), m.group(5)))
+        form = "vec" if m.group(4) == "true" else "scalar"
+        if m.group(5) == "true":
+            form += ",il"
+        return "gemm_nt<%s,%sx%s,%s> [%s]" % (t, m.group(2), m.group(3), form, FAMILIES.get(m.group(6), m.group(6)))
     m = re.search(r"rid::\(anonymous namespace\)::(\w+)", name)
     if m:
         return m.group(1)

@@ -65,3 +65,13 @@ def test_mfma_averages(tmp_path):
     text = out.read_text()
     assert "| k1 | 2 | 75.0 | 1.02, 0.00, 0.00 |" in text
     assert "| k2 |" not in text  # no matrix-core work
+
+
+def test_short_names_of_gemm_kernels():
+    from paper_2404_17133_amd.profsum import short_name
+
+    base = "void rid::(anonymous namespace)::gemm_nt_kernel<float, 64, 64, 32, 32, %s>(rid::GemmParams, int, long)"
+    assert short_name(base % "true, 3") == "gemm_nt<float,64x64,vec> [exch_w]"
+    assert short_name(base % "true, false, 3") == "gemm_nt<float,64x64,vec> [exch_w]"
+    assert short_name(base % "true, true, 5") == "gemm_nt<float,64x64,vec,il> [exch_wp]"
+    assert short_name(base % "false, false, 2") == "gemm_nt<float,64x64,scalar> [exch_s]"

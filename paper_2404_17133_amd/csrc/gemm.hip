@@ -5,9 +5,10 @@
 // Every K stage moves 128 bytes of K per operand row (32 f32, 16 f64, 64
 // bf16) from global memory to LDS, double-buffered with one barrier per
 // stage.  (Measured on gfx950: a second stage of register prefetch did not
-// help at these shapes.)  LDS rows are padded
-// by 16 bytes (stride 144 B) so that the 16-byte fragment reads of 16
-// consecutive rows hit distinct banks.  The K order inside a stage is
+// help at these shapes.)  The FP64 and BF16 tiles stage the loads through
+// registers into LDS rows padded by 16 bytes (stride 144 B), so that the
+// 16-byte fragment reads of 16 consecutive rows hit distinct banks; the FP32
+// tiles load straight into unpadded, XOR-swizzled LDS rows (gemm_tile_dma).  The K order inside a stage is
 // permuted so that each lane reads one contiguous slice per operand row: lane
 // group g (lanes sharing a row) takes the g-th slice of the stage, and MFMA
 // step s consumes the s-th element(s) of every group's slice.  Since A and B
@@ -24,6 +25,7 @@
 #include "gemm_limits.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace rid {
 namespace {
@@ -346,6 +348,243 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
   }
 }
 
+// The same tile with the operands moved from global memory straight into
+// LDS (buffer loads with an LDS destination: no staging registers and no LDS
+// stores by the waves), NSTG stage buffers.  Used for the FP32 tiles: on the
+// exchange shapes it matches the staged tile on 64x64 tiles and is 4-16 %
+// faster on 128x64 and 128x128 tiles; three or four buffers were slower
+// (fewer workgroups per CU).  LDS rows are not padded: chunk lc of row r sits
+// at chunk lc ^ sw(r), so that the 16-byte fragment reads of 16 consecutive
+// rows fall on distinct banks.  The MFMA steps consume the same K elements
+// in the same order as gemm_tile, so the two give identical results.
+__device__ __forceinline__ int lds_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+}
+
+template <typename T, int BM, int BN, int WM, int WN, bool IL, int NSTG>
+__device__ __forceinline__ void gemm_tile_dma(const GemmParams p, int tm, int tn, int z, int split) {
+  using At = Atom<T>;
+  using E_t = typename At::elem_t;
+  using V_t = typename At::vec_t;
+  using acc_t = typename At::acc_t;
+  using accv_t = typename At::accv_t;
+  constexpr int VW = 16 / (int)sizeof(E_t);
+  constexpr int BK = 8 * VW;
+  constexpr int ROWS = BM + BN;
+  constexpr int NI = ROWS / 32;              // load instructions per wave per stage
+  static_assert(ROWS % 32 == 0, "tile rows must be a multiple of 32");
+  constexpr int STG_BYTES = ROWS * 128;
+  constexpr int NWM = BM / WM;
+  constexpr int NWN = BN / WN;
+  static_assert(NWM * NWN == 4, "four waves per workgroup");
+  constexpr int AMN = WM / At::AM;
+  constexpr int ANN = WN / At::AM;
+  constexpr int SL = 8 / At::G;
+  constexpr int KSTEPS = BK / At::G / At::E;
+  constexpr int SPC = KSTEPS / SL;
+  static_assert(SPC * SL == KSTEPS, "steps per chunk");
+  static_assert(NSTG >= 2 && NSTG <= 4, "stage buffers");
+
+  __shared__ __attribute__((aligned(1024))) char lds[NSTG * STG_BYTES];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: LDS destinations go through M0
+  const int m0 = tm * BM;
+  const int n0 = tn * BN;
+  const int z1 = z / p.nz2, z2 = z % p.nz2;
+  const int pbeg = split * p.pps;
+  const int pend = min(p.np, pbeg + p.pps);
+  const E_t* Ab = reinterpret_cast<const E_t*>(p.A) + z1 * p.sA1 + z2 * p.sA2;
+  const E_t* Bb = reinterpret_cast<const E_t*>(p.B) + z1 * p.sB1 + z2 * p.sB2;
+  const int nkt = (p.K + BK - 1) / BK;
+  const int nstage = pend > pbeg ? (pend - pbeg) * nkt : 0;
+  const long lda = p.lda, ldb = p.ldb, sAp = p.sAp, sBp = p.sBp;
+  const int M = p.M, N = p.N, K = p.K;
+
+  // load instruction q of this wave covers stacked rows r0 .. r0 + 7 with
+  // r0 = (q * 4 + wave) * 8; lane i takes row r0 + i / 8, LDS chunk i % 8,
+  // which holds logical chunk (i % 8) ^ sw(row)
+  constexpr int kOob = (int)0x80000000;
+  int voff[NI], vlc[NI];
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    const int r = (q * 4 + wave) * 8 + (lane >> 3);
+    const int lc = (lane & 7) ^ lds_swz(r);
+    vlc[q] = lc;
+    const bool a_row = r < BM;
+    const int rr = a_row ? r : r - BM;
+    const bool ok = a_row ? (m0 + rr < M) : (n0 + rr < N);
+    const long ld = a_row ? lda : ldb;
+    voff[q] = ok ? (int)(((long)rr * ld + lc * VW) * (long)sizeof(E_t)) : kOob;
+  }
+  int pcur = pbeg, kcur = 0;  // batch and K position of the next stage to load
+  auto issue = [&](int buf) {
+    const E_t* abase = Ab + (long)pcur * sAp + (long)m0 * lda;
+    const E_t* bbase = Bb + (long)pcur * sBp + (long)n0 * ldb;
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<E_t*>(abase), (short)0, 0x7fffffff, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<E_t*>(bbase), (short)0, 0x7fffffff, 0x00020000);
+    const int soff = kcur * (int)sizeof(E_t);
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      const int r0 = (q * 4 + wave) * 8;  // wave-uniform
+      const bool kin = kcur + vlc[q] * VW < K;
+      char* dst = lds + buf * STG_BYTES + r0 * 128;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r0 < BM ? ra : rb, (__attribute__((address_space(3))) void*)dst, 16,
+                                               kin ? voff[q] : kOob, soff, 0, 0);
+    }
+    kcur += BK;
+    if (kcur >= nkt * BK) {
+      kcur = 0;
+      ++pcur;
+    }
+  };
+
+  const int wm = (wave % NWM) * WM;
+  const int wn = (wave / NWM) * WN;
+  const int lr = lane % At::AM;
+  const int g = lane / At::AM;
+  constexpr int CSTEP = IL ? At::G : 1;
+  const int cbase = IL ? g : g * SL;
+  // byte offsets (within a stage buffer) of the fragment chunks
+  int offa[AMN][SL], offb[ANN][SL];
+#pragma unroll
+  for (int i = 0; i < AMN; ++i) {
+    const int r = wm + i * At::AM + lr;
+#pragma unroll
+    for (int c = 0; c < SL; ++c) offa[i][c] = r * 128 + ((cbase + c * CSTEP) ^ lds_swz(r)) * 16;
+  }
+#pragma unroll
+  for (int j = 0; j < ANN; ++j) {
+    const int r = BM + wn + j * At::AM + lr;
+#pragma unroll
+    for (int c = 0; c < SL; ++c) offb[j][c] = r * 128 + ((cbase + c * CSTEP) ^ lds_swz(r)) * 16;
+  }
+
+  accv_t acc[AMN][ANN];
+#pragma unroll
+  for (int i = 0; i < AMN; ++i)
+#pragma unroll
+    for (int j = 0; j < ANN; ++j)
+#pragma unroll
+      for (int r = 0; r < At::NACC; ++r) acc[i][j][r] = acc_t(0);
+
+  auto compute = [&](int buf, int nc) {
+    const char* base = lds + buf * STG_BYTES;
+    V_t fa[AMN][SL];
+    V_t fb[ANN][SL];
+#pragma unroll
+    for (int i = 0; i < AMN; ++i)
+#pragma unroll
+      for (int c = 0; c < SL; ++c) fa[i][c] = *reinterpret_cast<const V_t*>(base + offa[i][c]);
+#pragma unroll
+    for (int j = 0; j < ANN; ++j)
+#pragma unroll
+      for (int c = 0; c < SL; ++c) fb[j][c] = *reinterpret_cast<const V_t*>(base + offb[j][c]);
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) {
+      if (IL && s % SPC == 0 && s / SPC >= nc) break;
+#pragma unroll
+      for (int i = 0; i < AMN; ++i)
+#pragma unroll
+        for (int j = 0; j < ANN; ++j) acc[i][j] = At::mma(At::op(fa[i], s), At::op(fb[j], s), acc[i][j]);
+    }
+  };
+
+  const acc_t alpha = (acc_t)p.alpha;
+  auto store_tile = [&](E_t* C) {
+#pragma unroll
+    for (int i = 0; i < AMN; ++i)
+#pragma unroll
+      for (int j = 0; j < ANN; ++j)
+#pragma unroll
+        for (int r = 0; r < At::NACC; ++r) {
+          const int m = m0 + wm + i * At::AM + At::row(lane, r);
+          const int n = n0 + wn + j * At::AM + lr;
+          if (m < p.M && n < p.N) C[(long)m * p.ldc + n] = At::out(alpha * acc[i][j][r]);
+        }
+  };
+  const bool each = p.mode == GEMM_STORE_EACH;
+  E_t* Ce = reinterpret_cast<E_t*>(p.C) + z1 * p.sC1 + z2 * p.sC2;
+
+  // NSTG - 1 stages in flight ahead of the one being computed.  At step t:
+  // wait for this wave's loads of stage t, barrier (every wave's loads of
+  // stage t are in LDS, and every wave is done reading the buffer of stage
+  // t - 1), refill that buffer with stage t + NSTG - 1, compute stage t.
+#pragma unroll
+  for (int q = 0; q < NSTG - 1; ++q)
+    if (q < nstage) issue(q);
+  int kt_c = 0, p_c = pbeg;
+  for (int t = 0; t < nstage; ++t) {
+    if (t + NSTG - 2 < nstage)
+      wait_vm<NI * (NSTG - 2)>();
+    else
+      wait_vm<0>();
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's reads of the previous buffer are done
+    __builtin_amdgcn_s_barrier();
+    if (t + NSTG - 1 < nstage) issue((t + NSTG - 1) % NSTG);
+    int nc = SL;
+    if constexpr (IL) {
+      const int valid = K - kt_c * BK;
+      if (valid < BK) nc = ((valid + VW - 1) / VW + At::G - 1) / At::G;
+    }
+    compute(t % NSTG, nc);
+    if (++kt_c == nkt) {
+      kt_c = 0;
+      if (each) {
+        store_tile(Ce + (long)p_c * p.sCs);
+#pragma unroll
+        for (int i = 0; i < AMN; ++i)
+#pragma unroll
+          for (int j = 0; j < ANN; ++j)
+#pragma unroll
+            for (int r = 0; r < At::NACC; ++r) acc[i][j][r] = acc_t(0);
+        ++p_c;
+      }
+    }
+  }
+  // every wave is past its last LDS read before the next tile refills them
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+
+  if (each) {
+    return;
+  } else if (p.mode == GEMM_STORE) {
+    store_tile(Ce);
+  } else {
+    acc_t* C = reinterpret_cast<acc_t*>(p.C) + split * p.sCs + z1 * p.sC1 + z2 * p.sC2;
+    const bool add = p.mode == GEMM_PARTIAL_ADD;
+#pragma unroll
+    for (int i = 0; i < AMN; ++i)
+#pragma unroll
+      for (int j = 0; j < ANN; ++j)
+#pragma unroll
+        for (int r = 0; r < At::NACC; ++r) {
+          const int m = m0 + wm + i * At::AM + At::row(lane, r);
+          const int n = n0 + wn + j * At::AM + lr;
+          if (m < p.M && n < p.N) {
+            acc_t* dst = C + (long)m * p.ldc + n;
+            const acc_t v = alpha * acc[i][j][r];
+            *dst = add ? *dst + v : v;
+          }
+        }
+  }
+}
+
+template <typename T, int BM, int BN, int WM, int WN, bool VEC, bool IL>
+__device__ __forceinline__ void gemm_tile_any(const GemmParams p, int tm, int tn, int z, int split) {
+  if constexpr (VEC && std::is_same<T, float>::value)
+    gemm_tile_dma<T, BM, BN, WM, WN, IL, 2>(p, tm, tn, z, split);
+  else
+    gemm_tile<T, BM, BN, WM, WN, VEC, IL>(p, tm, tn, z, split);
+}
+
 constexpr int kXcds = 8;
 
 // Position in the tile walk of workgroup w of a launch of `total`: the
@@ -390,7 +629,7 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_nt_kernel(GemmP
   const int tiles_n = (p.N + BN - 1) / BN;
   const int nsplit = (int)(total / ((long)tiles_m * tiles_n * nz));
   const TileCoord c = walk_decode(p.order, xcd_walk(blockIdx.x, total), tiles_m, tiles_n, nz, nsplit);
-  gemm_tile<T, BM, BN, WM, WN, VEC, IL>(p, c.tm, c.tn, c.z, c.split);
+  gemm_tile_any<T, BM, BN, WM, WN, VEC, IL>(p, c.tm, c.tn, c.z, c.split);
 }
 
 // Device descriptor of one member of a grouped launch.
@@ -421,7 +660,7 @@ __global__ __launch_bounds__(256, MinBlocks<T>::value) void gemm_grouped_kernel(
     const GemmParams p = gd[lo].p;
     const TileCoord c =
         walk_decode(p.order, t - gd[lo].begin, gd[lo].tiles_m, gd[lo].tiles_n, gd[lo].nz, gd[lo].nsplit);
-    gemm_tile<T, BM, BN, WM, WN, VEC, IL>(p, c.tm, c.tn, c.z, c.split);
+    gemm_tile_any<T, BM, BN, WM, WN, VEC, IL>(p, c.tm, c.tn, c.z, c.split);
   }
 }
 

@@ -5,10 +5,11 @@
 // Every K stage moves 128 bytes of K per operand row (32 f32, 16 f64, 64
 // bf16) from global memory to LDS, double-buffered with one barrier per
 // stage.  (Measured on gfx950: a second stage of register prefetch did not
-// help at these shapes.)  The FP64 and BF16 tiles stage the loads through
-// registers into LDS rows padded by 16 bytes (stride 144 B), so that the
-// 16-byte fragment reads of 16 consecutive rows hit distinct banks; the FP32
-// tiles load straight into unpadded, XOR-swizzled LDS rows (gemm_tile_dma).  The K order inside a stage is
+// help at these shapes.)  With 16-byte vector loads the tiles load straight
+// into unpadded, XOR-swizzled LDS rows (gemm_tile_dma); the scalar-load form
+// (unaligned or odd operands) stages the loads through registers into LDS
+// rows padded by 16 bytes (stride 144 B), so that the 16-byte fragment reads
+// of 16 consecutive rows hit distinct banks.  The K order inside a stage is
 // permuted so that each lane reads one contiguous slice per operand row: lane
 // group g (lanes sharing a row) takes the g-th slice of the stage, and MFMA
 // step s consumes the s-th element(s) of every group's slice.  Since A and B
@@ -350,10 +351,11 @@ __device__ __forceinline__ void gemm_tile(const GemmParams p, int tm, int tn, in
 
 // The same tile with the operands moved from global memory straight into
 // LDS (buffer loads with an LDS destination: no staging registers and no LDS
-// stores by the waves), NSTG stage buffers.  Used for the FP32 tiles: on the
-// exchange shapes it matches the staged tile on 64x64 tiles and is 4-16 %
-// faster on 128x64 and 128x128 tiles; three or four buffers were slower
-// (fewer workgroups per CU).  LDS rows are not padded: chunk lc of row r sits
+// stores by the waves), NSTG stage buffers.  Used for every vector-load
+// tile: on the FP32 exchange shapes it matches the staged tile on 64x64
+// tiles and is 4-16 % faster on 128x64 and 128x128 tiles, and the FP64
+// step is 7 % faster; three or four buffers were slower (fewer workgroups
+// per CU).  LDS rows are not padded: chunk lc of row r sits
 // at chunk lc ^ sw(r), so that the 16-byte fragment reads of 16 consecutive
 // rows fall on distinct banks.  The MFMA steps consume the same K elements
 // in the same order as gemm_tile, so the two give identical results.
@@ -579,7 +581,7 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmParams p, int tm, int tn
 
 template <typename T, int BM, int BN, int WM, int WN, bool VEC, bool IL>
 __device__ __forceinline__ void gemm_tile_any(const GemmParams p, int tm, int tn, int z, int split) {
-  if constexpr (VEC && std::is_same<T, float>::value)
+  if constexpr (VEC)
     gemm_tile_dma<T, BM, BN, WM, WN, IL, 2>(p, tm, tn, z, split);
   else
     gemm_tile<T, BM, BN, WM, WN, VEC, IL>(p, tm, tn, z, split);

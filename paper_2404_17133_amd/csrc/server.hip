@@ -17,6 +17,7 @@
 // ends.  Result timestamps (arrival, admission, completion) are in
 // milliseconds on the server's steady clock.
 #include <algorithm>
+#include <cstdlib>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -159,7 +160,13 @@ rid_status batch_run(rid_context* ctx, int n, rid_problem* const* probs, const r
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return request_weight(probs[a], reqs[a]) > request_weight(probs[b], reqs[b]);
   });
-  const int nworkers = std::min(n, 16);
+  // concurrent solves: 16, or RID_BATCH_WORKERS (1..64; a tuning knob)
+  static const int max_workers = [] {
+    const char* e = std::getenv("RID_BATCH_WORKERS");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 1 && v <= 64 ? v : 16;
+  }();
+  const int nworkers = std::min(n, max_workers);
   // Two ends of the weight order: even workers take the heaviest request
   // left, odd workers the lightest.  The heavy solves keep the matrix cores
   // busy while the light ones, latency-bound, run in their gaps, instead of

@@ -38,3 +38,32 @@ def test_traffic_lookup_matches_the_committed_counter_summary(monkeypatch):
     # once the GEMM source changes, the old counters no longer describe it
     monkeypatch.setattr(profsum, "gemm_source_hash", lambda: "0" * 16)
     assert bench.measured_traffic("exch_w", "f32", "c2") is None
+
+
+def test_stored_bench_line_keeps_the_contract():
+    """The committed no=200 bench line (written by a GPU run of bench.py) has
+    every field of the one-line JSON contract, a roofline of the dominant
+    kernel whose fraction is achieved / peak, and a CPU baseline of the
+    oracle; the values are consistent with each other."""
+    import json
+
+    line = json.load(open(os.path.join(ROOT, "profiles", "exch_contractions_c2_mixed_bench_line.json")))["line"]
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert key in line, key
+    assert line["n_gpus"] == 1 and line["higher_is_better"] is True and line["data"] == "synthetic"
+    assert "workload" in line["config"]
+    # value = solutions per second over the timed steps
+    per_step = line["config"]["roots_per_step"]
+    assert abs(line["value"] - per_step / (line["ms_per_step"] / 1000.0)) < 1e-3 * line["value"]
+    rf = line["roofline"]
+    for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert key in rf, key
+    assert rf["bound"] in ("hbm", "mfma", "alu") and rf["peak"] == 157.3 and rf["unit"] == "TFLOP/s"
+    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
+    # achieved = algorithmic flops per launch over the measured launch time
+    assert abs(rf["achieved"] - rf["flops_per_launch"] / (rf["avg_launch_ms"] * 1e-3) / 1e12) < 0.01 * rf["achieved"]
+    cb = line["cpu_baseline"]
+    for key in ("value", "unit", "cores", "kind", "sample"):
+        assert key in cb, key
+    assert cb["kind"] == "oracle" and cb["unit"] == line["unit"] and cb["cores"] >= 1
